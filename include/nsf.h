@@ -1,0 +1,222 @@
+/*
+ * nsf.h -- C ABI of the MI355X null-space-free Maxwell eigensolver.
+ *
+ * The library solves the discrete Maxwell GEP on a Yee grid,
+ *     diag(C, C^*) [E; H] = omega * i [[zeta_d, mu_d], [-eps_d, -xi_d]] [E; H]
+ * (Sec. 3), through the null-space-free HHPD pencil of Thm 4.2,
+ *     B_r y = omega^{-1} A_r y,
+ *     A_r = diag(P_r^*, Q_r^*) L diag(Phi^{-1}, mu_d^{-1}) L^* diag(P_r, Q_r),
+ *     B_r = i [[0, Sigma_r^{-1}], [-Sigma_r^{-1}, 0]],
+ * where C = P_r Sigma_r Q_r^* is the SVD of the single-curl operator
+ * (Thm 2.5).  P_r and Q_r are applied with twisted 3-D FFTs (Sec. 4.2), the
+ * linear systems with A_r are solved by conjugate gradients (Sec. 4.2) and the
+ * pencil by invert Lanczos with thick restarts (Sec. 4.2, Algorithm 1).
+ *
+ * Conventions (all calls):
+ *  - Every function returns an int status (NSF_OK = 0).  Nothing throws or
+ *    aborts across this boundary.  nsf_last_error() gives a message.
+ *  - Complex numbers are nsf_c128 {re, im} (layout of hipDoubleComplex).
+ *  - Grid index g = i1 + n1*i2 + n1*n2*i3 (x fastest), the Kronecker order of
+ *    C_1 = delta_x^{-1} (I (x) I (x) K) (Sec. 2).  Frequency index f uses the
+ *    same order over (i1, i2, i3), i_l in [0, n_l).
+ *  - A 3n field vector is [x-component; y-component; z-component], n each.
+ *  - A 4n pencil vector is y = [y_a; y_b; y_c; y_d], n each, frequency order;
+ *    [y_a; y_b] multiplies P_r = [P_2, P_1] and [y_c; y_d] multiplies
+ *    Q_r = [Q_1, Q_2] (Thm 2.5).
+ *  - Pointers marked "device" are HIP device pointers; the call enqueues its
+ *    work on the plan's stream and returns without waiting unless it returns
+ *    host results.  Pointers marked "host" are ordinary host memory.
+ *  - The caller owns every buffer it passes.  The plan owns its tables and its
+ *    workspace (hipMalloc'd lazily, freed by nsf_plan_destroy).
+ *  - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef NSF_H
+#define NSF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nsf_plan_s* nsf_plan;
+typedef struct { double re, im; } nsf_c128;
+
+/* Solver counters returned by nsf_eigs / nsf_cg_solve. */
+typedef struct {
+  long long matvecs;         /* A_r applies (CG iterations + exact applies)     */
+  long long cg_iters_total;  /* CG iterations over all solves                   */
+  int cg_solves;             /* number of CG solves                             */
+  int lanczos_steps;         /* basis expansions                                */
+  int restarts;              /* thick restarts                                  */
+  int converged;             /* wanted pairs with residual <= res_tol           */
+  double cg_iters_avg;       /* cg_iters_total / cg_solves                      */
+  double ms_total;           /* wall time of the call (host clock)              */
+  double bytes_alg;          /* algorithmic HBM bytes of the A_r applies        */
+} nsf_stats;
+
+enum {
+  NSF_OK = 0,
+  NSF_NOT_CONVERGED = 1,  /* results filled; residuals tell which pairs        */
+  NSF_E_ARG = -1,         /* bad size, pointer or parameter                    */
+  NSF_E_KPOINT = -2,      /* Lambda_q singular: every k_l * a is an integer    */
+  NSF_E_BASIS = -3,       /* alpha, beta make Lambda_p rank deficient          */
+  NSF_E_NOT_HHPD = -4,    /* mu_d or Phi not HPD, or xi^* != zeta (Sec. 4.1)   */
+  NSF_E_BREAKDOWN = -5,   /* CG: p^* A_r p <= 0 or not finite                  */
+  NSF_E_NOMEM = -6,       /* device allocation failed                          */
+  NSF_E_HIP = -7,         /* HIP runtime error                                 */
+  NSF_E_STATE = -8        /* call needs state the plan does not have yet       */
+};
+
+/* Medium kinds reported by nsf_plan_query. */
+enum { NSF_MEDIUM_NONE = 0, NSF_MEDIUM_CHIRAL = 1, NSF_MEDIUM_PSEUDOCHIRAL = 2 };
+
+/*
+ * Create a plan for one Bloch vector on an n1 x n2 x n3 Yee grid of the simple
+ * cubic lattice a_l = a e_l (Sec. 1), mesh delta_l = a / n_l.
+ *   k[3]        Bloch vector in reciprocal units (2 pi k is the wave vector);
+ *               the twist e^{i 2 pi k_l a} closes K_{a,m} (Sec. 2).
+ *   alpha, beta the free entries of a = (alpha, beta, 1) in Lambda_p
+ *               (Lemma 2.2); the spectrum does not depend on them.
+ *   hip_stream  hipStream_t to enqueue on (NULL: the null stream).
+ * Host-only: validates and builds the per-axis tables; no device call is made
+ * until device work is requested.  Errors: NSF_E_ARG (n_l < 2 or > 512 or with
+ * a prime factor other than 2, 3, 5; a <= 0; out == NULL), NSF_E_KPOINT
+ * (sigma_f = 0 for some f, i.e. all k_l a integer, Lemma 2.2 (a)),
+ * NSF_E_BASIS (Lambda_p has a zero column, Lemma 2.2 (b)).
+ */
+int nsf_plan_create(nsf_plan* out, int n1, int n2, int n3, double a,
+                    const double k[3], double alpha, double beta,
+                    void* hip_stream);
+
+/* Free the plan and all device memory it owns.  NULL is accepted. */
+void nsf_plan_destroy(nsf_plan plan);
+
+/*
+ * Query plan facts (host).  Any output pointer may be NULL.
+ *   n              n1*n2*n3
+ *   medium_kind    NSF_MEDIUM_*
+ *   sigma_min/max  extreme singular values sigma_f = Lambda_q^{1/2} (Thm 2.5)
+ */
+int nsf_plan_query(nsf_plan plan, long long* n, int* medium_kind,
+                   double* sigma_min, double* sigma_max);
+
+/*
+ * Chiral medium (Sec. 4.3): eps_d = diag(eps), mu_d = I, xi_d = i diag(gamma),
+ * zeta_d = -i diag(gamma), per voxel g (length n each, float64).  host or
+ * device pointers (on_device = 0 / 1); device data is copied.  Validation of
+ * host data (Sec. 4.1 assumption; Phi = eps - gamma^2 > 0, all finite) happens
+ * before any device call: NSF_E_NOT_HHPD or NSF_E_ARG.  Device data is
+ * validated by a kernel and the call synchronises the stream.
+ */
+int nsf_set_medium_chiral(nsf_plan plan, const double* eps, const double* gamma,
+                          int on_device);
+
+/*
+ * Pseudochiral medium (Sec. 4.3): xi_d = i gamma (e_a e_b^T + e_b e_a^T),
+ * zeta_d = xi_d^*, mu_d = I, eps_d = diag(eps); axis_a != axis_b in {0,1,2}
+ * (0 = x).  Phi = diag(eps - gamma^2 on axes a and b, eps on the third) must
+ * be positive.  Errors as nsf_set_medium_chiral.
+ */
+int nsf_set_medium_pseudochiral(nsf_plan plan, int axis_a, int axis_b,
+                                const double* eps, const double* gamma,
+                                int on_device);
+
+/*
+ * Basis applies (Thm 2.5; T by twisted FFT, Sec. 4.2).  All pointers device.
+ *   nsf_apply_Pr : y (2n, [y_a; y_b]) -> x (3n) = P_r y
+ *   nsf_apply_Qr : y (2n, [y_c; y_d]) -> x (3n) = Q_r y
+ *   nsf_apply_PrH: x (3n) -> y (2n) = P_r^* x
+ *   nsf_apply_QrH: x (3n) -> y (2n) = Q_r^* x
+ * Input and output must not overlap.  Asynchronous on the plan's stream.
+ */
+int nsf_apply_Pr(nsf_plan plan, const nsf_c128* y2n, nsf_c128* x3n);
+int nsf_apply_Qr(nsf_plan plan, const nsf_c128* y2n, nsf_c128* x3n);
+int nsf_apply_PrH(nsf_plan plan, const nsf_c128* x3n, nsf_c128* y2n);
+int nsf_apply_QrH(nsf_plan plan, const nsf_c128* x3n, nsf_c128* y2n);
+
+/*
+ * out = A_r u (Thm 4.2, the operator of the linear systems in Sec. 4.2).
+ * u and out are device 4n vectors and must not overlap.  Needs a medium
+ * (NSF_E_STATE otherwise).  Asynchronous.
+ */
+int nsf_apply_Ar(nsf_plan plan, const nsf_c128* u4n, nsf_c128* out4n);
+
+/* out = B_r u (Thm 4.2).  Device 4n vectors, may alias.  Asynchronous. */
+int nsf_apply_Br(nsf_plan plan, const nsf_c128* u4n, nsf_c128* out4n);
+
+/*
+ * Solve A_r x = b by unpreconditioned CG from x = 0 (Sec. 4.2), stopping when
+ * ||r||_2 <= rtol ||b||_2 (the recurrence residual) or after maxit iterations.
+ * b, x: device 4n vectors (distinct).  iters, relres: host outputs (nullable).
+ * Synchronises the stream.  Returns NSF_OK, NSF_NOT_CONVERGED (maxit hit) or
+ * NSF_E_BREAKDOWN.
+ */
+int nsf_cg_solve(nsf_plan plan, const nsf_c128* b, nsf_c128* x, double rtol,
+                 int maxit, int* iters, double* relres);
+
+/*
+ * The nev smallest positive eigenvalues omega of the GEP (Sec. 3), i.e. the
+ * nev largest theta = 1/omega of B_r y = theta A_r y, by invert Lanczos in the
+ * A_r inner product with thick restarts and CG inner solves (Sec. 4.2,
+ * Algorithm 1 step 5).
+ *   nev          1 <= nev <= 256
+ *   res_tol      stop when every wanted pair has
+ *                eta = ||B_r y - theta A_r y|| / (|theta| ||A_r y||) <= res_tol
+ *   cg_rtol      relative tolerance of the inner CG solves
+ *   max_basis    Lanczos basis size m before a restart (0: 3*nev, at least
+ *                nev + 8); m + 1 vectors of 4n are kept, plus A_r times them
+ *   max_restarts 0: no limit other than 1000
+ *   seed         start vector seed (complex normal from a counter hash)
+ *   omega_host   host, nev doubles, ascending (reported as the pencil
+ *                Rayleigh quotient of each Ritz vector)
+ *   Y_dev        device 4n x nev (column j at Y_dev + j*4n), A_r-orthonormal
+ *                Ritz vectors; nullable
+ *   resid_host   host, nev residuals eta; nullable
+ *   stats        nullable
+ * Synchronises the stream.  Returns NSF_OK or NSF_NOT_CONVERGED (results still
+ * filled), or an error.
+ */
+int nsf_eigs(nsf_plan plan, int nev, double res_tol, double cg_rtol,
+             int max_basis, int max_restarts, unsigned long long seed,
+             double* omega_host, nsf_c128* Y_dev, double* resid_host,
+             nsf_stats* stats);
+
+/*
+ * Gradient of S = sum_j w_j omega_j with respect to the per-voxel eps and
+ * gamma of a chiral medium, by the Hellmann-Feynman rule for the HHPD pencil
+ * (Thm 4.2): d omega = omega y^* dA_r y for A_r-normalised y.  With
+ * E' = P_r y_P, H' = Q_r y_Q per voxel and Phi = eps - gamma^2:
+ *   d omega/d eps_g   = -omega sum_c |i gamma E'_c + H'_c|^2 / Phi^2
+ *   d omega/d gamma_g =  omega sum_c [2 Re(conj(i gamma E'_c + H'_c) i E'_c)/Phi
+ *                                     + 2 gamma |i gamma E'_c + H'_c|^2 / Phi^2]
+ *   nev          number of eigenpairs
+ *   omega_host   host, nev eigenvalues
+ *   Y_dev        device 4n x nev, A_r-orthonormal eigenvectors (nsf_eigs)
+ *   weights_host host, nev weights w_j (dS/d omega_j)
+ *   d_eps_dev, d_gamma_dev  device, n doubles each, overwritten
+ * Needs a chiral medium (NSF_E_STATE otherwise).  Asynchronous.
+ */
+int nsf_eig_grad(nsf_plan plan, int nev, const double* omega_host,
+                 const nsf_c128* Y_dev, const double* weights_host,
+                 double* d_eps_dev, double* d_gamma_dev);
+
+/*
+ * Dense Hermitian eigensolver on the host (cyclic complex Jacobi), the small
+ * projected problem of the Lanczos method.  H: host m x m, row-major, only read.
+ * w: host m ascending eigenvalues.  V: host m x m, row-major, column j is the
+ * eigenvector of w[j] (nullable).  1 <= m <= 512.
+ */
+int nsf_hermitian_eig(int m, const nsf_c128* H, double* w, nsf_c128* V);
+
+/* Text for a status code (static storage). */
+const char* nsf_status_string(int status);
+
+/* Last error message of this plan (or of the last plan-less call if NULL). */
+const char* nsf_last_error(nsf_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSF_H */

@@ -1,0 +1,410 @@
+// Vector kernels: fixed-order reductions, the CG recurrences (Sec. 4.2) and
+// the multi-vector products of the Lanczos basis.
+//
+// Reductions are deterministic: every launch uses the same grid, every thread
+// sums a fixed strided slice, waves reduce with butterfly shuffles and a
+// single workgroup folds the per-workgroup partials in a fixed order.  No
+// floating-point atomics are used.
+#include "nsf_internal.h"
+
+namespace nsf {
+namespace {
+
+constexpr int kRedThreads = 256;
+
+__device__ inline double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+// Sum over the workgroup; the result is valid in thread 0.
+__device__ inline double2 block_sum(double2 v) {
+  __shared__ double2 red[kRedThreads / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double2 s = make_double2(0, 0);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = cadd(s, red[i]);
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ inline double2 fold_partials(const double2* partial, int nparts) {
+  double2 v = make_double2(0, 0);
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v = cadd(v, partial[i]);
+  return block_sum(v);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_dot(const double2* __restrict__ x,
+                                                     const double2* __restrict__ y, long long len,
+                                                     double2* partial, const int* skip) {
+  if (skip && *skip) return;
+  double2 acc = make_double2(0, 0);
+  for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < len;
+       i += (long long)gridDim.x * kRedThreads)
+    acc = cadd(acc, cmulc(x[i], y[i]));
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double2* partial, int nparts,
+                                                        double2* out) {
+  const double2 s = fold_partials(partial, nparts);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+// ------------------------------------------------------------------ CG
+__global__ __launch_bounds__(kRedThreads) void k_cg_init(const double2* __restrict__ b,
+                                                         double2* __restrict__ x,
+                                                         double2* __restrict__ r,
+                                                         double2* __restrict__ p, long long len,
+                                                         double2* partial) {
+  double2 acc = make_double2(0, 0);
+  for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < len;
+       i += (long long)gridDim.x * kRedThreads) {
+    const double2 v = b[i];
+    x[i] = make_double2(0, 0);
+    r[i] = v;
+    p[i] = v;
+    acc.x += cabs2(v);
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_cg_init_final(const double2* partial, int nparts,
+                                                               CgState* st, double rtol,
+                                                               int maxit) {
+  const double2 s = fold_partials(partial, nparts);
+  if (threadIdx.x == 0) {
+    const double bb = s.x;
+    st->bb = bb;
+    st->rr = bb;
+    st->thresh = rtol * rtol * bb;
+    st->alpha = 0;
+    st->beta = 0;
+    st->iter = 0;
+    st->maxit = maxit;
+    st->status = NSF_OK;
+    st->done = 0;
+    if (!(bb > 0.0)) {
+      st->done = 1;
+      st->status = (bb == 0.0) ? NSF_OK : NSF_E_BREAKDOWN;  // zero rhs, or NaN
+    } else if (maxit <= 0) {
+      st->done = 1;
+      st->status = NSF_NOT_CONVERGED;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_cg_alpha(const double2* partial, int nparts,
+                                                          CgState* st) {
+  if (st->done) return;
+  const double2 s = fold_partials(partial, nparts);
+  if (threadIdx.x == 0) {
+    const double pq = s.x;  // p^* A_r p is real for Hermitian A_r
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      st->status = NSF_E_BREAKDOWN;
+      st->done = 1;
+    } else {
+      st->alpha = st->rr / pq;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_cg_update(double2* __restrict__ x,
+                                                           double2* __restrict__ r,
+                                                           const double2* __restrict__ p,
+                                                           const double2* __restrict__ q,
+                                                           long long len, double2* partial,
+                                                           const CgState* st) {
+  if (st->done) return;
+  const double al = st->alpha;
+  double2 acc = make_double2(0, 0);
+  for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < len;
+       i += (long long)gridDim.x * kRedThreads) {
+    const double2 pi = p[i], qi = q[i];
+    double2 xi = x[i], ri = r[i];
+    xi = make_double2(xi.x + al * pi.x, xi.y + al * pi.y);
+    ri = make_double2(ri.x - al * qi.x, ri.y - al * qi.y);
+    x[i] = xi;
+    r[i] = ri;
+    acc.x += cabs2(ri);
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_cg_beta(const double2* partial, int nparts,
+                                                         CgState* st) {
+  if (st->done) return;
+  const double2 s = fold_partials(partial, nparts);
+  if (threadIdx.x == 0) {
+    const double rr_new = s.x;
+    st->iter += 1;
+    st->beta = rr_new / st->rr;
+    st->rr = rr_new;
+    if (!isfinite(rr_new)) {
+      st->status = NSF_E_BREAKDOWN;
+      st->done = 1;
+    } else if (rr_new <= st->thresh) {
+      st->status = NSF_OK;
+      st->done = 1;
+    } else if (st->iter >= st->maxit) {
+      st->status = NSF_NOT_CONVERGED;
+      st->done = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_cg_p(double2* __restrict__ p,
+                                                      const double2* __restrict__ r, long long len,
+                                                      const CgState* st) {
+  if (st->done) return;
+  const double be = st->beta;
+  for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < len;
+       i += (long long)gridDim.x * kRedThreads) {
+    const double2 pi = p[i], ri = r[i];
+    p[i] = make_double2(ri.x + be * pi.x, ri.y + be * pi.y);
+  }
+}
+
+// ------------------------------------------------------- multi-vector ops
+constexpr int kDotChunk = 4;  // basis vectors per workgroup of the multi-dot
+
+__global__ __launch_bounds__(kRedThreads) void k_multi_dot(const double2* __restrict__ V,
+                                                           long long ld, int m,
+                                                           const double2* __restrict__ w,
+                                                           long long len, double2* partial) {
+  const int i0 = blockIdx.y * kDotChunk;
+  double2 acc[kDotChunk];
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) acc[c] = make_double2(0, 0);
+  for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < len;
+       e += (long long)gridDim.x * kRedThreads) {
+    const double2 we = w[e];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c)
+      if (i0 + c < m) acc[c] = cadd(acc[c], cmulc(V[(i0 + c) * ld + e], we));
+  }
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) {
+    const double2 s = block_sum(acc[c]);
+    if (threadIdx.x == 0 && i0 + c < m) partial[(long long)(i0 + c) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_multi_dot_final(const double2* partial, int nparts,
+                                                                 double2* out) {
+  const double2 s = fold_partials(partial + (long long)blockIdx.x * nparts, nparts);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_multi_axpy(const double2* __restrict__ V,
+                                                            long long ld, int m,
+                                                            const double2* __restrict__ c,
+                                                            double2* __restrict__ w,
+                                                            long long len) {
+  __shared__ double2 cs[512];
+  for (int i = threadIdx.x; i < m; i += kRedThreads) cs[i] = c[i];
+  __syncthreads();
+  for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < len;
+       e += (long long)gridDim.x * kRedThreads) {
+    double2 acc = w[e];
+    for (int i = 0; i < m; ++i) acc = csub(acc, cmul(cs[i], V[i * ld + e]));
+    w[e] = acc;
+  }
+}
+
+// In-place V[:, 0:k] = V[:, 0:m] S for a slab of `cols` elements at a time:
+// the slab of all m vectors is read into LDS before any of it is overwritten.
+__global__ __launch_bounds__(kRedThreads) void k_rotate(double2* V, long long ld, int m, int k,
+                                                        const double2* __restrict__ S,
+                                                        long long len, int kRotCols) {
+  extern __shared__ double2 slab[];  // m * kRotCols
+  const long long e0 = (long long)blockIdx.x * kRotCols;
+  for (int t = threadIdx.x; t < m * kRotCols; t += kRedThreads) {
+    const int i = t / kRotCols, e = t - i * kRotCols;
+    slab[t] = (e0 + e < len) ? V[i * ld + e0 + e] : make_double2(0, 0);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < k * kRotCols; t += kRedThreads) {
+    const int c = t / kRotCols, e = t - c * kRotCols;
+    if (e0 + e >= len) continue;
+    double2 acc = make_double2(0, 0);
+    for (int i = 0; i < m; ++i) acc = cadd(acc, cmul(slab[i * kRotCols + e], S[c * m + i]));
+    V[c * ld + e0 + e] = acc;
+  }
+}
+
+__global__ void k_scale_copy(const double2* __restrict__ x, double2* __restrict__ y, double sre,
+                             double sim, long long len) {
+  const double2 s = make_double2(sre, sim);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = cmul(s, x[i]);
+}
+
+// splitmix64 finaliser: a counter-based hash of (seed, index).
+__device__ inline unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_randn(double2* v, long long len, unsigned long long seed) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long h1 = mix64(seed ^ mix64(2ull * (unsigned long long)i));
+    const unsigned long long h2 = mix64(seed ^ mix64(2ull * (unsigned long long)i + 1ull));
+    const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);  // (0,1)
+    const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(6.283185307179586476925 * u2, &sn, &cs);
+    v[i] = make_double2(rad * cs, rad * sn);
+  }
+}
+
+// Per frequency: (B_r u)_a = i u_c/s, _b = i u_d/s, _c = -i u_a/s, _d = -i u_b/s.
+__global__ __launch_bounds__(kRedThreads) void k_residual(Geom g, Tables t,
+                                                          const double2* __restrict__ u,
+                                                          const double2* __restrict__ Au,
+                                                          double theta, double2* partial) {
+  const long long n = g.n;
+  double2 acc = make_double2(0, 0);
+  for (long long f = blockIdx.x * (long long)kRedThreads + threadIdx.x; f < n;
+       f += (long long)gridDim.x * kRedThreads) {
+    const int i1 = (int)(f % g.n1);
+    const int i2 = (int)((f / g.n1) % g.n2);
+    const int i3 = (int)(f / ((long long)g.n1 * g.n2));
+    const double s2 = cabs2(t.lam[i1]) + cabs2(t.lam[g.n1 + i2]) + cabs2(t.lam[g.n1 + g.n2 + i3]);
+    const double is = 1.0 / sqrt(s2);
+    const double2 ua = u[f], ub = u[n + f], uc = u[2 * n + f], ud = u[3 * n + f];
+    const double2 B[4] = {cscale(cmuli(uc), is), cscale(cmuli(ud), is), cscale(cmuli(ua), -is),
+                          cscale(cmuli(ub), -is)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 a = Au[q * n + f];
+      acc.x += cabs2(csub(B[q], cscale(a, theta)));
+      acc.y += cabs2(a);
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+int red_grid(long long len) {
+  long long b = (len + kRedThreads - 1) / kRedThreads;
+  return (int)(b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks);
+}
+
+int ew_grid(long long len) {
+  long long b = (len + 255) / 256;
+  return (int)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+}
+
+}  // namespace
+
+hipError_t launch_dot_partials(const double2* x, const double2* y, long long len, double2* partial,
+                               const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(red_grid(len)), dim3(kRedThreads), 0, s, x, y, len, partial, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double2* partial, int nparts, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, partial, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const double2* b, double2* x, double2* r, double2* p, long long len,
+                          double2* partial, CgState* st, double rtol, int maxit, hipStream_t s) {
+  const int nb = red_grid(len);
+  hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, b, x, r, p, len, partial);
+  hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kRedThreads), 0, s, partial, nb, st, rtol, maxit);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha(const double2* partial, int nparts, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kRedThreads), 0, s, partial, nparts, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double2* x, double2* r, const double2* p, const double2* q,
+                            long long len, double2* partial, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(red_grid(len)), dim3(kRedThreads), 0, s, x, r, p, q, len,
+                     partial, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_beta(const double2* partial, int nparts, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kRedThreads), 0, s, partial, nparts, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_p(double2* p, const double2* r, long long len, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p, dim3(red_grid(len)), dim3(kRedThreads), 0, s, p, r, len, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2* w, long long len,
+                            double2* partial, double2* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  int nb = red_grid(len);
+  if (nb > 256) nb = 256;
+  const dim3 grid(nb, (m + kDotChunk - 1) / kDotChunk);
+  hipLaunchKernelGGL(k_multi_dot, grid, dim3(kRedThreads), 0, s, V, ld, m, w, len, partial);
+  hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(kRedThreads), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
+                             long long len, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_multi_axpy, dim3(ew_grid(len)), dim3(kRedThreads), 0, s, V, ld, m, c, w, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate(double2* V, long long ld, int m, int k, const double2* S, long long len,
+                         hipStream_t s) {
+  int cols = 4096 / m;
+  if (cols > 32) cols = 32;
+  if (cols < 1) cols = 1;
+  const long long blocks = (len + cols - 1) / cols;
+  const size_t lds = sizeof(double2) * (size_t)m * cols;
+  hipLaunchKernelGGL(k_rotate, dim3((unsigned)blocks), dim3(kRedThreads), lds, s, V, ld, m, k, S, len,
+                     cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const double2* x, double2* y, double sre, double sim, long long len,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(ew_grid(len)), dim3(256), 0, s, x, y, sre, sim, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_randn(double2* v, long long len, unsigned long long seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_randn, dim3(ew_grid(len)), dim3(256), 0, s, v, len, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_norms(const Geom& g, const Tables& t, const double2* u, const double2* Au,
+                                 double theta, double2* partial, double* out2, hipStream_t s) {
+  const int nb = red_grid(g.n);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kRedThreads), 0, s, g, t, u, Au, theta, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, partial, nb,
+                     reinterpret_cast<double2*>(out2));
+  return hipGetLastError();
+}
+
+int reduce_parts_for(long long len) { return red_grid(len); }
+
+}  // namespace nsf

@@ -1,0 +1,228 @@
+// Internal declarations shared by the HIP sources of libnsf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nsf.h"
+
+namespace nsf {
+
+constexpr int kMaxAxis = 512;    // longest supported axis (six fields of one pencil fit a tile)
+constexpr int kMaxStages = 10;   // radix stages per axis
+constexpr int kThreads = 256;    // threads per workgroup of the FFT passes
+constexpr int kEpt = 16;         // complex elements per thread held in registers
+
+// ---------------------------------------------------------------- complex ops
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__host__ __device__ inline double2 cmulc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i * a
+__host__ __device__ inline double2 cmuli(double2 a) { return make_double2(-a.y, a.x); }
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------------------------ FFT plan
+// Mixed-radix Stockham factorisation of one axis (radices 8, 4, 2, 3, 5).
+struct AxisPlan {
+  int N;
+  int nst;
+  int radix[kMaxStages];
+};
+
+// Per-frequency basis data needs the three per-axis lambda tables; the twist
+// tables d_l(j) = exp(i 2 pi k_l a j / n_l) are needed only by P_r, Q_r alone.
+struct Tables {
+  const double2* lam;    // n1 + n2 + n3 values: lambda_1 | lambda_2 | lambda_3
+  const double2* twist;  // n1 + n2 + n3 values: d_1 | d_2 | d_3
+  const double2* tw;     // n1 + n2 + n3 FFT roots exp(+2 pi i m / n_l) per axis
+};
+
+struct Geom {
+  int n1, n2, n3;
+  long long n;
+  double alpha, beta;
+};
+
+enum MediumKind { kMedNone = 0, kMedChiral = 1, kMedPseudo = 2 };
+
+struct MediumView {
+  int kind;
+  int pa, pb, po;        // pseudochiral coupled axes and the third axis
+  const double2* eg;     // per voxel (eps, gamma)
+};
+
+// Which half of the synthesis / projection a pass performs.
+enum BasisPart { kPartBoth = 0, kPartP = 1, kPartQ = 2 };
+
+// ------------------------------------------------------------- launch layer
+// All launchers enqueue on `s` and return hipError_t of the launch.
+// `skip` (nullable, device): when *skip != 0 every workgroup exits at once.
+
+// Synthesis (P_r / Q_r coefficients) fused with the inverse x-FFT.
+// y: [y_a; y_b; y_c; y_d] blocks (n each); part selects which blocks are read
+// and which fields are written: kPartBoth -> fld[0..5]; kPartP -> fld[0..2]
+// from (y_a, y_b) = y[0], y[n]; kPartQ -> fld[0..2] from (y_c, y_d) passed as
+// y[0], y[n].
+hipError_t launch_x_inv_synth(const Geom& g, const AxisPlan& ax, const Tables& t,
+                              int part, const double2* y, double2* fld,
+                              const int* skip, hipStream_t s);
+
+// Plain FFT along y (axis 1) or z (axis 2) of nf fields in place.
+// dir = +1 inverse (e^{+}), -1 forward (e^{-}).  post_twist: multiply the result
+// by D_g / sqrt(n) (inverse z pass of P_r / Q_r).  pre_twist: multiply the input
+// by conj(D_g) / sqrt(n) (forward z pass of P_r^* / Q_r^*).
+hipError_t launch_yz_pass(const Geom& g, const AxisPlan& ax, const Tables& t, int axis,
+                          int dir, int nf, double2* fld, int post_twist, int pre_twist,
+                          const int* skip, hipStream_t s);
+
+// Inverse z-FFT, per-voxel constitutive step (times 1/n), forward z-FFT of the
+// six fields [E'x E'y E'z H'x H'y H'z] in place.
+hipError_t launch_z_mid(const Geom& g, const AxisPlan& ax, const Tables& t,
+                        const MediumView& med, double2* fld, const int* skip,
+                        hipStream_t s);
+
+// Forward x-FFT fused with the projection P_r^* / Q_r^*.  kPartBoth: fields
+// 0..5 -> out blocks a, b, c, d; kPartP: fields 0..2 -> out blocks a, b;
+// kPartQ: fields 0..2 -> out blocks c, d (written at out[0], out[n]).
+hipError_t launch_x_fwd_proj(const Geom& g, const AxisPlan& ax, const Tables& t,
+                             int part, const double2* fld, double2* out,
+                             const int* skip, hipStream_t s);
+
+// out = B_r u (Thm 4.2): per frequency 1/sigma_f times i / -i block swaps.
+hipError_t launch_apply_Br(const Geom& g, const Tables& t, const double2* u, double2* out,
+                           const int* skip, hipStream_t s);
+
+// -------------------------------------------------------------- BLAS layer
+constexpr int kRedBlocks = 1024;       // partial-sum slots for one reduction
+constexpr int kPartialSlots = 131072;  // partial-sum slots of the multi-vector dot (512 x 256)
+constexpr int kCoefSlots = 1024;       // device coefficient vector of the Lanczos steps
+
+struct CgState {
+  double rr;        // r^* r of the current iterate
+  double thresh;    // (rtol ||b||)^2
+  double bb;        // ||b||^2
+  double alpha, beta;
+  int iter, maxit;
+  int done;         // nonzero: every CG kernel exits at once
+  int status;       // NSF_OK / NSF_NOT_CONVERGED / NSF_E_BREAKDOWN
+  int pad[3];
+};
+
+// partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
+hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,
+                               double2* partial, const int* skip, hipStream_t s);
+hipError_t launch_cg_init(const double2* b, double2* x, double2* r, double2* p, long long len,
+                          double2* partial, CgState* st, double rtol, int maxit, hipStream_t s);
+hipError_t launch_cg_alpha(const double2* partial, int nparts, CgState* st, hipStream_t s);
+hipError_t launch_cg_update(double2* x, double2* r, const double2* p, const double2* q,
+                            long long len, double2* partial, CgState* st, hipStream_t s);
+hipError_t launch_cg_beta(const double2* partial, int nparts, CgState* st, hipStream_t s);
+// Number of partial sums the reductions above write for a vector of length len.
+int reduce_parts_for(long long len);
+hipError_t launch_cg_p(double2* p, const double2* r, long long len, CgState* st, hipStream_t s);
+
+// Multi-vector kernels for the Lanczos basis (vectors at stride ld).
+// c[i] = sum_e conj(V_i[e]) w[e], i < m, written as m complex values to out.
+hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2* w, long long len,
+                            double2* partial, double2* out, hipStream_t s);
+// w -= sum_i c[i] V_i  (c on device, m complex)
+hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
+                             long long len, hipStream_t s);
+// V[:, 0:k] = V[:, 0:m] S (S device, m x k column-major complex), in place.
+hipError_t launch_rotate(double2* V, long long ld, int m, int k, const double2* S, long long len,
+                         hipStream_t s);
+// y = a * x  (complex scalar on host)
+hipError_t launch_scale_copy(const double2* x, double2* y, double sre, double sim, long long len,
+                             hipStream_t s);
+// Complex normal vector from a counter-based hash of (seed, index).
+hipError_t launch_randn(double2* v, long long len, unsigned long long seed, hipStream_t s);
+// out[0] = sum |B u - theta A u|^2, out[1] = sum |A u|^2, with Bu computed on the fly.
+hipError_t launch_residual_norms(const Geom& g, const Tables& t, const double2* u,
+                                 const double2* Au, double theta, double2* partial,
+                                 double* out2, hipStream_t s);
+// Reduce kRedBlocks complex partials to one complex value at out.
+hipError_t launch_reduce_partials(const double2* partial, int nparts, double2* out, hipStream_t s);
+
+// Gradient accumulation (chiral): after the inverse passes have produced
+// E', H' (spatial fields with the 1/sqrt(n) scaling), accumulate
+// d_eps += w*omega*(...), d_gamma += w*omega*(...).
+hipError_t launch_grad_accum(const Geom& g, const double2* eg, const double2* fld, double wo,
+                             double* d_eps, double* d_gamma, int first, hipStream_t s);
+
+}  // namespace nsf
+
+// The opaque plan.
+struct nsf_plan_s {
+  nsf::Geom geom;
+  double a;
+  double k[3];
+  double delta[3];
+  nsf::AxisPlan ax[3];
+  hipStream_t stream = nullptr;
+  int device = -1;
+  bool dev_ready = false;
+  double sigma_min = 0, sigma_max = 0;
+
+  // host tables
+  std::vector<double2> h_lam, h_twist, h_tw;
+  // device tables
+  double2* d_tables = nullptr;  // lam | twist | tw
+  nsf::Tables tabs{};
+
+  // medium
+  int medium_kind = nsf::kMedNone;
+  int pa = 0, pb = 1, po = 2;
+  double2* d_medium = nullptr;  // (eps, gamma) per voxel
+
+  // workspace
+  double2* d_fields = nullptr;  // 6 n
+  double2* d_cg = nullptr;      // x r p q : 4 x 4n (cg scratch)
+  double2* d_partial = nullptr; // kPartialSlots partial sums
+  double2* d_coef = nullptr;    // kCoefSlots complex coefficients (multi-dot results)
+  double2* d_res = nullptr;     // 64 complex reduction results
+  double2* d_small = nullptr;   // small dense matrices (Ritz rotations)
+  size_t small_cap = 0;
+  nsf::CgState* d_state = nullptr;
+  nsf::CgState* h_state = nullptr;  // pinned
+  int* d_flags = nullptr;           // misc device ints
+  int* h_flags = nullptr;           // pinned
+
+  // Lanczos basis storage
+  double2* d_basis = nullptr;  // V and AV
+  size_t basis_vectors = 0;    // capacity of V (and of AV)
+
+  std::string last_error;
+};
+
+// Return the library status of a failed HIP call from the enclosing function.
+#define NSF_HIP(p, call)                                      \
+  do {                                                        \
+    const int _rc = ::nsf::hip_check((p), (call), #call);     \
+    if (_rc != NSF_OK) return _rc;                            \
+  } while (0)
+
+namespace nsf {
+// Host helpers (plan.hip)
+int ensure_device(nsf_plan p);
+int set_error(nsf_plan p, int code, const std::string& msg);
+int hip_check(nsf_plan p, hipError_t e, const char* what);
+MediumView medium_view(nsf_plan p);
+int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip);
+int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
+                 double* relres, long long* matvecs);
+int ensure_basis(nsf_plan p, size_t vectors);
+int ensure_small(nsf_plan p, size_t count);
+int hermitian_eig(int m, const double2* H, double* w, double2* V);
+}  // namespace nsf

@@ -1,0 +1,392 @@
+// Plan construction, medium upload and the basis / A_r / B_r applies (host).
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "nsf_internal.h"
+
+namespace {
+thread_local std::string g_plain_error;  // errors of calls without a plan
+
+long double kPi = 3.141592653589793238462643383279502884L;
+
+// exp(i 2 pi num / den) evaluated with the phase reduced in long double.
+double2 unit_phase(long double num, long double den) {
+  long double t = num / den;
+  t -= floorl(t);
+  const long double ang = 2.0L * kPi * t;
+  return make_double2((double)cosl(ang), (double)sinl(ang));
+}
+
+bool factor_axis(int N, nsf::AxisPlan& ax) {
+  ax.N = N;
+  ax.nst = 0;
+  int m = N;
+  for (int r : {8, 4, 2, 3, 5}) {
+    while (m % r == 0) {
+      if (ax.nst >= nsf::kMaxStages) return false;
+      ax.radix[ax.nst++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+}  // namespace
+
+namespace nsf {
+
+int set_error(nsf_plan p, int code, const std::string& msg) {
+  if (p) p->last_error = msg;
+  else g_plain_error = msg;
+  return code;
+}
+
+int hip_check(nsf_plan p, hipError_t e, const char* what) {
+  if (e == hipSuccess) return NSF_OK;
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  const int code = (e == hipErrorOutOfMemory) ? NSF_E_NOMEM : NSF_E_HIP;
+  return set_error(p, code, msg);
+}
+
+int ensure_device(nsf_plan p) {
+  if (p->dev_ready) return NSF_OK;
+  NSF_HIP(p, hipGetDevice(&p->device));
+  const Geom& g = p->geom;
+  const size_t ntab = (size_t)g.n1 + g.n2 + g.n3;
+  NSF_HIP(p, hipMalloc(&p->d_tables, sizeof(double2) * 3 * ntab));
+  std::vector<double2> all;
+  all.reserve(3 * ntab);
+  all.insert(all.end(), p->h_lam.begin(), p->h_lam.end());
+  all.insert(all.end(), p->h_twist.begin(), p->h_twist.end());
+  all.insert(all.end(), p->h_tw.begin(), p->h_tw.end());
+  NSF_HIP(p, hipMemcpy(p->d_tables, all.data(), sizeof(double2) * all.size(), hipMemcpyHostToDevice));
+  p->tabs.lam = p->d_tables;
+  p->tabs.twist = p->d_tables + ntab;
+  p->tabs.tw = p->d_tables + 2 * ntab;
+  NSF_HIP(p, hipMalloc(&p->d_fields, sizeof(double2) * 6 * (size_t)g.n));
+  NSF_HIP(p, hipMalloc(&p->d_partial, sizeof(double2) * (size_t)(kPartialSlots + kCoefSlots + 64)));
+  p->d_coef = p->d_partial + kPartialSlots;
+  p->d_res = p->d_coef + kCoefSlots;
+  NSF_HIP(p, hipMalloc(&p->d_state, sizeof(CgState)));
+  NSF_HIP(p, hipHostMalloc(&p->h_state, sizeof(CgState)));
+  NSF_HIP(p, hipMalloc(&p->d_flags, sizeof(int) * 16));
+  NSF_HIP(p, hipMemset(p->d_flags, 0, sizeof(int) * 16));
+  NSF_HIP(p, hipHostMalloc(&p->h_flags, sizeof(int) * 16));
+  p->dev_ready = true;
+  return NSF_OK;
+}
+
+MediumView medium_view(nsf_plan p) {
+  MediumView m;
+  m.kind = p->medium_kind;
+  m.pa = p->pa;
+  m.pb = p->pb;
+  m.po = p->po;
+  m.eg = p->d_medium;
+  return m;
+}
+
+// A_r u in five passes: [synthesis + inverse x] [inverse y]
+// [inverse z, middle factor, forward z] [forward y] [forward x + projection].
+int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip) {
+  const Geom& g = p->geom;
+  hipStream_t s = p->stream;
+  double2* F = p->d_fields;
+  NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartBoth, u, F, skip, s));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 6, F, 0, 0, skip, s));
+  NSF_HIP(p, launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), F, skip, s));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, -1, 6, F, 0, 0, skip, s));
+  NSF_HIP(p, launch_x_fwd_proj(g, p->ax[0], p->tabs, kPartBoth, F, out, skip, s));
+  return NSF_OK;
+}
+
+}  // namespace nsf
+
+using namespace nsf;
+
+extern "C" {
+
+const char* nsf_status_string(int status) {
+  switch (status) {
+    case NSF_OK: return "ok";
+    case NSF_NOT_CONVERGED: return "not converged";
+    case NSF_E_ARG: return "invalid argument";
+    case NSF_E_KPOINT: return "Bloch vector makes Lambda_q singular";
+    case NSF_E_BASIS: return "alpha, beta make Lambda_p rank deficient";
+    case NSF_E_NOT_HHPD: return "medium violates mu > 0, Phi > 0, xi^* = zeta";
+    case NSF_E_BREAKDOWN: return "CG breakdown (p^*Ap <= 0 or not finite)";
+    case NSF_E_NOMEM: return "device out of memory";
+    case NSF_E_HIP: return "HIP runtime error";
+    case NSF_E_STATE: return "plan is missing required state";
+    default: return "unknown status";
+  }
+}
+
+const char* nsf_last_error(nsf_plan plan) {
+  return plan ? plan->last_error.c_str() : g_plain_error.c_str();
+}
+
+int nsf_plan_create(nsf_plan* out, int n1, int n2, int n3, double a, const double k[3], double alpha,
+                    double beta, void* hip_stream) {
+  if (!out) return set_error(nullptr, NSF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!k) return set_error(nullptr, NSF_E_ARG, "k is NULL");
+  const int dims[3] = {n1, n2, n3};
+  AxisPlan ax[3];
+  for (int l = 0; l < 3; ++l) {
+    if (dims[l] < 2 || dims[l] > kMaxAxis || !factor_axis(dims[l], ax[l]))
+      return set_error(nullptr, NSF_E_ARG,
+                       "grid size " + std::to_string(dims[l]) +
+                           " unsupported (2..512, prime factors 2, 3, 5 only)");
+  }
+  if (!(a > 0.0) || !std::isfinite(a)) return set_error(nullptr, NSF_E_ARG, "lattice constant a must be > 0");
+  if (!std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]))
+    return set_error(nullptr, NSF_E_ARG, "k must be finite");
+  if (!std::isfinite(alpha) || !std::isfinite(beta) || alpha == 0.0 || beta == 0.0)
+    return set_error(nullptr, NSF_E_ARG, "alpha and beta must be finite and nonzero (Lemma 2.2)");
+
+  auto* p = new (std::nothrow) nsf_plan_s();
+  if (!p) return set_error(nullptr, NSF_E_NOMEM, "host allocation failed");
+  p->geom.n1 = n1;
+  p->geom.n2 = n2;
+  p->geom.n3 = n3;
+  p->geom.n = (long long)n1 * n2 * n3;
+  p->geom.alpha = alpha;
+  p->geom.beta = beta;
+  p->a = a;
+  for (int l = 0; l < 3; ++l) {
+    p->k[l] = k[l];
+    p->delta[l] = a / dims[l];
+    p->ax[l] = ax[l];
+  }
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+
+  // Per-axis tables.  lambda_l(i) = (exp(i 2 pi (i + k_l a)/n_l) - 1)/delta_l
+  // (Thm 2.1), evaluated as (-2 sin^2(t/2) + i sin t)/delta_l so that small
+  // phases keep their relative accuracy; twist d_l(j) = exp(i 2 pi k_l a j/n_l)
+  // (D_{a,m}); FFT roots exp(2 pi i m / n_l).
+  double smin2 = 0, smax2 = 0;
+  for (int l = 0; l < 3; ++l) {
+    const int m = dims[l];
+    double amin = 1e300, amax = 0;
+    for (int i = 0; i < m; ++i) {
+      long double t = ((long double)i + (long double)k[l] * (long double)a) / (long double)m;
+      t -= floorl(t);
+      const long double ang = 2.0L * kPi * t;
+      const long double sh = sinl(0.5L * ang);
+      const double re = (double)(-2.0L * sh * sh / (long double)p->delta[l]);
+      const double im = (double)(sinl(ang) / (long double)p->delta[l]);
+      p->h_lam.push_back(make_double2(re, im));
+      const double a2 = re * re + im * im;
+      amin = std::min(amin, a2);
+      amax = std::max(amax, a2);
+    }
+    smin2 += amin;
+    smax2 += amax;
+  }
+  for (int l = 0; l < 3; ++l)
+    for (int j = 0; j < dims[l]; ++j)
+      p->h_twist.push_back(unit_phase((long double)k[l] * (long double)a * j, (long double)dims[l]));
+  for (int l = 0; l < 3; ++l)
+    for (int j = 0; j < dims[l]; ++j) p->h_tw.push_back(unit_phase(j, dims[l]));
+  p->sigma_min = std::sqrt(smin2);
+  p->sigma_max = std::sqrt(smax2);
+  // Lemma 2.2 (a): Lambda_q > 0.  sigma^2 is a sum of per-axis terms, so its
+  // minimum is the sum of the per-axis minima.
+  if (!(p->sigma_min > 1e-12 * p->sigma_max)) {
+    delete p;
+    return set_error(nullptr, NSF_E_KPOINT, "Lambda_q is singular: every k_l * a is an integer");
+  }
+  // Lemma 2.2 (b): every column p_f = a x lambda_f of Lambda_p nonzero.
+  {
+    const double2* l1 = p->h_lam.data();
+    const double2* l2 = l1 + n1;
+    const double2* l3 = l2 + n2;
+    double worst = 1e300;
+    for (int i3 = 0; i3 < n3; ++i3)
+      for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1) {
+          const double2 p1 = csub(cscale(l3[i3], beta), l2[i2]);
+          const double2 p2 = csub(l1[i1], cscale(l3[i3], alpha));
+          const double2 p3 = csub(cscale(l2[i2], alpha), cscale(l1[i1], beta));
+          const double s2 = cabs2(l1[i1]) + cabs2(l2[i2]) + cabs2(l3[i3]);
+          const double r = (cabs2(p1) + cabs2(p2) + cabs2(p3)) / ((alpha * alpha + beta * beta + 1.0) * s2);
+          worst = std::min(worst, r);
+        }
+    if (!(worst > 1e-24)) {
+      delete p;
+      return set_error(nullptr, NSF_E_BASIS, "Lambda_p has a (near) zero column for these alpha, beta");
+    }
+  }
+  *out = p;
+  return NSF_OK;
+}
+
+void nsf_plan_destroy(nsf_plan p) {
+  if (!p) return;
+  if (p->dev_ready) {
+    hipStreamSynchronize(p->stream);
+    hipFree(p->d_tables);
+    hipFree(p->d_fields);
+    hipFree(p->d_partial);
+    hipFree(p->d_state);
+    hipHostFree(p->h_state);
+    hipFree(p->d_flags);
+    hipHostFree(p->h_flags);
+    if (p->d_medium) hipFree(p->d_medium);
+    if (p->d_cg) hipFree(p->d_cg);
+    if (p->d_basis) hipFree(p->d_basis);
+    if (p->d_small) hipFree(p->d_small);
+  }
+  delete p;
+}
+
+int nsf_plan_query(nsf_plan p, long long* n, int* medium_kind, double* sigma_min, double* sigma_max) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  if (n) *n = p->geom.n;
+  if (medium_kind) *medium_kind = p->medium_kind;
+  if (sigma_min) *sigma_min = p->sigma_min;
+  if (sigma_max) *sigma_max = p->sigma_max;
+  return NSF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host validation of (eps, gamma) against the assumption of Sec. 4.1 for the
+// compact media: mu = I > 0, xi^* = zeta holds by construction, and Phi > 0
+// (chiral: eps - gamma^2; pseudochiral: eps - gamma^2 and eps).
+int validate_eg(nsf_plan p, const double* eps, const double* gam, long long n) {
+  for (long long g = 0; g < n; ++g) {
+    const double e = eps[g], c = gam[g];
+    if (!std::isfinite(e) || !std::isfinite(c))
+      return set_error(p, NSF_E_ARG, "medium has a non-finite value at voxel " + std::to_string(g));
+    if (!(e - c * c > 0.0) || !(e > 0.0))
+      return set_error(p, NSF_E_NOT_HHPD,
+                       "Phi = eps - gamma^2 is not positive at voxel " + std::to_string(g));
+  }
+  return NSF_OK;
+}
+
+int set_medium(nsf_plan p, int kind, int pa, int pb, const double* eps, const double* gam,
+               int on_device) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  if (!eps || !gam) return set_error(p, NSF_E_ARG, "eps or gamma is NULL");
+  const long long n = p->geom.n;
+  std::vector<double> he, hg;
+  const double* e = eps;
+  const double* c = gam;
+  if (on_device) {
+    int rc = ensure_device(p);
+    if (rc) return rc;
+    he.resize(n);
+    hg.resize(n);
+    NSF_HIP(p, hipMemcpyAsync(he.data(), eps, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream));
+    NSF_HIP(p, hipMemcpyAsync(hg.data(), gam, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream));
+    NSF_HIP(p, hipStreamSynchronize(p->stream));
+    e = he.data();
+    c = hg.data();
+  }
+  int rc = validate_eg(p, e, c, n);
+  if (rc) return rc;
+  rc = ensure_device(p);
+  if (rc) return rc;
+  std::vector<double2> packed(n);
+  for (long long g = 0; g < n; ++g) packed[g] = make_double2(e[g], c[g]);
+  if (!p->d_medium) NSF_HIP(p, hipMalloc(&p->d_medium, sizeof(double2) * n));
+  NSF_HIP(p, hipMemcpyAsync(p->d_medium, packed.data(), sizeof(double2) * n, hipMemcpyHostToDevice,
+                            p->stream));
+  NSF_HIP(p, hipStreamSynchronize(p->stream));
+  p->medium_kind = kind;
+  p->pa = pa;
+  p->pb = pb;
+  p->po = 3 - pa - pb;
+  return NSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nsf_set_medium_chiral(nsf_plan p, const double* eps, const double* gamma, int on_device) {
+  return set_medium(p, kMedChiral, 0, 1, eps, gamma, on_device);
+}
+
+int nsf_set_medium_pseudochiral(nsf_plan p, int axis_a, int axis_b, const double* eps,
+                                const double* gamma, int on_device) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  if (axis_a < 0 || axis_a > 2 || axis_b < 0 || axis_b > 2 || axis_a == axis_b)
+    return set_error(p, NSF_E_ARG, "pseudochiral axes must be two distinct values in {0,1,2}");
+  return set_medium(p, kMedPseudo, std::min(axis_a, axis_b), std::max(axis_a, axis_b), eps, gamma,
+                    on_device);
+}
+
+int nsf_apply_Pr(nsf_plan p, const nsf_c128* y2n, nsf_c128* x3n) {
+  if (!p || !y2n || !x3n) return set_error(p, NSF_E_ARG, "NULL argument");
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  const Geom& g = p->geom;
+  auto* x = reinterpret_cast<double2*>(x3n);
+  NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartP, reinterpret_cast<const double2*>(y2n), x,
+                                nullptr, p->stream));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 3, x, 0, 0, nullptr, p->stream));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[2], p->tabs, 2, +1, 3, x, 1, 0, nullptr, p->stream));
+  return NSF_OK;
+}
+
+int nsf_apply_Qr(nsf_plan p, const nsf_c128* y2n, nsf_c128* x3n) {
+  if (!p || !y2n || !x3n) return set_error(p, NSF_E_ARG, "NULL argument");
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  const Geom& g = p->geom;
+  auto* x = reinterpret_cast<double2*>(x3n);
+  NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartQ, reinterpret_cast<const double2*>(y2n), x,
+                                nullptr, p->stream));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 3, x, 0, 0, nullptr, p->stream));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[2], p->tabs, 2, +1, 3, x, 1, 0, nullptr, p->stream));
+  return NSF_OK;
+}
+
+static int apply_adjoint(nsf_plan p, int part, const nsf_c128* x3n, nsf_c128* y2n) {
+  if (!p || !x3n || !y2n) return set_error(p, NSF_E_ARG, "NULL argument");
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  const Geom& g = p->geom;
+  double2* F = p->d_fields;
+  NSF_HIP(p, hipMemcpyAsync(F, x3n, sizeof(double2) * 3 * g.n, hipMemcpyDeviceToDevice, p->stream));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[2], p->tabs, 2, -1, 3, F, 0, 1, nullptr, p->stream));
+  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, -1, 3, F, 0, 0, nullptr, p->stream));
+  NSF_HIP(p, launch_x_fwd_proj(g, p->ax[0], p->tabs, part, F, reinterpret_cast<double2*>(y2n), nullptr,
+                               p->stream));
+  return NSF_OK;
+}
+
+int nsf_apply_PrH(nsf_plan p, const nsf_c128* x3n, nsf_c128* y2n) {
+  return apply_adjoint(p, kPartP, x3n, y2n);
+}
+
+int nsf_apply_QrH(nsf_plan p, const nsf_c128* x3n, nsf_c128* y2n) {
+  return apply_adjoint(p, kPartQ, x3n, y2n);
+}
+
+int nsf_apply_Ar(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n) {
+  if (!p || !u4n || !out4n) return set_error(p, NSF_E_ARG, "NULL argument");
+  if (p->medium_kind == kMedNone) return set_error(p, NSF_E_STATE, "no medium set");
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  return apply_Ar_dev(p, reinterpret_cast<const double2*>(u4n), reinterpret_cast<double2*>(out4n),
+                      nullptr);
+}
+
+int nsf_apply_Br(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n) {
+  if (!p || !u4n || !out4n) return set_error(p, NSF_E_ARG, "NULL argument");
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, reinterpret_cast<const double2*>(u4n),
+                             reinterpret_cast<double2*>(out4n), nullptr, p->stream));
+  return NSF_OK;
+}
+
+}  // extern "C"

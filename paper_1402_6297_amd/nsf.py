@@ -1,0 +1,308 @@
+"""Python binding of libnsf (include/nsf.h): argument marshalling only.
+
+Each ``nsf_*`` function here calls the C function of the same name.  Device
+buffers are torch tensors on a HIP device (complex128 / float64, contiguous);
+host buffers are numpy arrays.  A nonzero error status raises ``NsfError``
+(``NSF_NOT_CONVERGED`` is returned, not raised, by the solvers).  Nothing here
+computes any part of the method: if libnsf.so is missing the first call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnsf.so")
+
+NSF_OK = 0
+NSF_NOT_CONVERGED = 1
+NSF_E_ARG = -1
+NSF_E_KPOINT = -2
+NSF_E_BASIS = -3
+NSF_E_NOT_HHPD = -4
+NSF_E_BREAKDOWN = -5
+NSF_E_NOMEM = -6
+NSF_E_HIP = -7
+NSF_E_STATE = -8
+
+EXPORTED = [
+    "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query",
+    "nsf_set_medium_chiral", "nsf_set_medium_pseudochiral",
+    "nsf_apply_Pr", "nsf_apply_Qr", "nsf_apply_PrH", "nsf_apply_QrH",
+    "nsf_apply_Ar", "nsf_apply_Br", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
+    "nsf_hermitian_eig", "nsf_status_string", "nsf_last_error",
+]
+
+
+class nsf_stats(C.Structure):
+    _fields_ = [("matvecs", C.c_longlong), ("cg_iters_total", C.c_longlong),
+                ("cg_solves", C.c_int), ("lanczos_steps", C.c_int), ("restarts", C.c_int),
+                ("converged", C.c_int), ("cg_iters_avg", C.c_double), ("ms_total", C.c_double),
+                ("bytes_alg", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NsfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libnsf.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1402_6297_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, I, D, VP = C.c_void_p, C.c_int, C.c_double, C.c_void_p
+    DP = C.POINTER(C.c_double)
+    sig = {
+        "nsf_plan_create": (I, [C.POINTER(P), I, I, I, D, DP, D, D, VP]),
+        "nsf_plan_destroy": (None, [P]),
+        "nsf_plan_query": (I, [P, C.POINTER(C.c_longlong), C.POINTER(I), DP, DP]),
+        "nsf_set_medium_chiral": (I, [P, VP, VP, I]),
+        "nsf_set_medium_pseudochiral": (I, [P, I, I, VP, VP, I]),
+        "nsf_apply_Pr": (I, [P, VP, VP]),
+        "nsf_apply_Qr": (I, [P, VP, VP]),
+        "nsf_apply_PrH": (I, [P, VP, VP]),
+        "nsf_apply_QrH": (I, [P, VP, VP]),
+        "nsf_apply_Ar": (I, [P, VP, VP]),
+        "nsf_apply_Br": (I, [P, VP, VP]),
+        "nsf_cg_solve": (I, [P, VP, VP, D, I, C.POINTER(I), DP]),
+        "nsf_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, VP, DP, C.POINTER(nsf_stats)]),
+        "nsf_eig_grad": (I, [P, I, DP, VP, DP, VP, VP]),
+        "nsf_hermitian_eig": (I, [I, VP, DP, VP]),
+        "nsf_status_string": (C.c_char_p, [I]),
+        "nsf_last_error": (C.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status, plan=None):
+    if status < 0:
+        msg = lib().nsf_last_error(plan)
+        raise NsfError(status, (msg or b"").decode() or lib().nsf_status_string(status).decode())
+    return status
+
+
+def _dptr(t, dtype_name):
+    """Device pointer of a contiguous torch tensor of the given dtype."""
+    import torch
+
+    want = {"c128": torch.complex128, "f64": torch.float64}[dtype_name]
+    if not isinstance(t, torch.Tensor) or t.dtype != want or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {want} tensor on a HIP device")
+    return C.c_void_p(t.data_ptr())
+
+
+def _hptr(a, dtype=np.float64):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, C.c_void_p(a.ctypes.data)
+
+
+def current_stream():
+    """hipStream_t of torch's current stream (0 if no device is visible)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        return 0
+    return torch.cuda.current_stream().cuda_stream
+
+
+# --------------------------------------------------------------------- calls
+
+def nsf_plan_create(n1, n2, n3, a, k, alpha=-1.0, beta=2.0, stream=None):
+    plan = C.c_void_p()
+    kk = (C.c_double * 3)(*[float(x) for x in k])
+    s = current_stream() if stream is None else stream
+    _check(lib().nsf_plan_create(C.byref(plan), int(n1), int(n2), int(n3), float(a), kk,
+                                 float(alpha), float(beta), C.c_void_p(s)))
+    return plan
+
+
+def nsf_plan_destroy(plan):
+    lib().nsf_plan_destroy(plan)
+
+
+def nsf_plan_query(plan):
+    n, kind = C.c_longlong(), C.c_int()
+    smin, smax = C.c_double(), C.c_double()
+    _check(lib().nsf_plan_query(plan, C.byref(n), C.byref(kind), C.byref(smin), C.byref(smax)), plan)
+    return dict(n=n.value, medium_kind=kind.value, sigma_min=smin.value, sigma_max=smax.value)
+
+
+def _medium_ptrs(eps, gamma):
+    try:
+        import torch
+        if isinstance(eps, torch.Tensor):
+            return (eps, gamma), _dptr(eps, "f64"), _dptr(gamma, "f64"), 1
+    except ImportError:  # pragma: no cover
+        pass
+    e, pe = _hptr(np.ravel(eps))
+    g, pg = _hptr(np.ravel(gamma))
+    return (e, g), pe, pg, 0
+
+
+def nsf_set_medium_chiral(plan, eps, gamma):
+    keep, pe, pg, on_dev = _medium_ptrs(eps, gamma)
+    return _check(lib().nsf_set_medium_chiral(plan, pe, pg, on_dev), plan)
+
+
+def nsf_set_medium_pseudochiral(plan, axis_a, axis_b, eps, gamma):
+    keep, pe, pg, on_dev = _medium_ptrs(eps, gamma)
+    return _check(lib().nsf_set_medium_pseudochiral(plan, int(axis_a), int(axis_b), pe, pg, on_dev), plan)
+
+
+def _apply(name, plan, src, dst):
+    return _check(getattr(lib(), name)(plan, _dptr(src, "c128"), _dptr(dst, "c128")), plan)
+
+
+def nsf_apply_Pr(plan, y2n, x3n):
+    return _apply("nsf_apply_Pr", plan, y2n, x3n)
+
+
+def nsf_apply_Qr(plan, y2n, x3n):
+    return _apply("nsf_apply_Qr", plan, y2n, x3n)
+
+
+def nsf_apply_PrH(plan, x3n, y2n):
+    return _apply("nsf_apply_PrH", plan, x3n, y2n)
+
+
+def nsf_apply_QrH(plan, x3n, y2n):
+    return _apply("nsf_apply_QrH", plan, x3n, y2n)
+
+
+def nsf_apply_Ar(plan, u4n, out4n):
+    return _apply("nsf_apply_Ar", plan, u4n, out4n)
+
+
+def nsf_apply_Br(plan, u4n, out4n):
+    return _apply("nsf_apply_Br", plan, u4n, out4n)
+
+
+def nsf_cg_solve(plan, b, x, rtol=1e-10, maxit=10000):
+    it, rel = C.c_int(), C.c_double()
+    st = _check(lib().nsf_cg_solve(plan, _dptr(b, "c128"), _dptr(x, "c128"), float(rtol), int(maxit),
+                                   C.byref(it), C.byref(rel)), plan)
+    return st, it.value, rel.value
+
+
+def nsf_eigs(plan, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, max_restarts=0, seed=0, Y=None):
+    """Returns (status, omega[nev], resid[nev], stats dict); Y (4n x nev device) is filled if given."""
+    omega = np.zeros(nev)
+    resid = np.zeros(nev)
+    st = nsf_stats()
+    yp = _dptr(Y, "c128") if Y is not None else None
+    status = _check(lib().nsf_eigs(plan, int(nev), float(res_tol), float(cg_rtol), int(max_basis),
+                                   int(max_restarts), C.c_ulonglong(seed),
+                                   omega.ctypes.data_as(C.POINTER(C.c_double)), yp,
+                                   resid.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)), plan)
+    return status, omega, resid, st.as_dict()
+
+
+def nsf_eig_grad(plan, omega, Y, weights, d_eps, d_gamma):
+    om, _ = _hptr(omega)
+    w, _ = _hptr(weights)
+    return _check(lib().nsf_eig_grad(plan, len(om), om.ctypes.data_as(C.POINTER(C.c_double)),
+                                     _dptr(Y, "c128"), w.ctypes.data_as(C.POINTER(C.c_double)),
+                                     _dptr(d_eps, "f64"), _dptr(d_gamma, "f64")), plan)
+
+
+def nsf_hermitian_eig(H):
+    H = np.ascontiguousarray(H, dtype=np.complex128)
+    m = H.shape[0]
+    w = np.zeros(m)
+    V = np.zeros((m, m), dtype=np.complex128)
+    _check(lib().nsf_hermitian_eig(m, C.c_void_p(H.ctypes.data), w.ctypes.data_as(C.POINTER(C.c_double)),
+                                   C.c_void_p(V.ctypes.data)))
+    return w, V
+
+
+def nsf_status_string(status):
+    return lib().nsf_status_string(int(status)).decode()
+
+
+def nsf_last_error(plan=None):
+    return (lib().nsf_last_error(plan) or b"").decode()
+
+
+# ------------------------------------------------------------ convenience
+
+class Plan:
+    """Owns an ``nsf_plan``; frees it on ``close()`` / garbage collection."""
+
+    def __init__(self, grid, k, a=1.0, alpha=-1.0, beta=2.0, stream=None):
+        self.grid = tuple(int(x) for x in grid)
+        self.k = tuple(float(x) for x in k)
+        self.a, self.alpha, self.beta = float(a), float(alpha), float(beta)
+        self.n = self.grid[0] * self.grid[1] * self.grid[2]
+        self.handle = nsf_plan_create(*self.grid, self.a, self.k, self.alpha, self.beta, stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            nsf_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def query(self):
+        return nsf_plan_query(self.handle)
+
+    def set_chiral(self, eps, gamma):
+        return nsf_set_medium_chiral(self.handle, eps, gamma)
+
+    def set_pseudochiral(self, axis_a, axis_b, eps, gamma):
+        return nsf_set_medium_pseudochiral(self.handle, axis_a, axis_b, eps, gamma)
+
+    def Ar(self, u, out):
+        return nsf_apply_Ar(self.handle, u, out)
+
+    def Br(self, u, out):
+        return nsf_apply_Br(self.handle, u, out)
+
+    def Pr(self, y, x):
+        return nsf_apply_Pr(self.handle, y, x)
+
+    def Qr(self, y, x):
+        return nsf_apply_Qr(self.handle, y, x)
+
+    def PrH(self, x, y):
+        return nsf_apply_PrH(self.handle, x, y)
+
+    def QrH(self, x, y):
+        return nsf_apply_QrH(self.handle, x, y)
+
+    def cg(self, b, x, rtol=1e-10, maxit=10000):
+        return nsf_cg_solve(self.handle, b, x, rtol, maxit)
+
+    def eigs(self, nev, **kw):
+        return nsf_eigs(self.handle, nev, **kw)
+
+    def eig_grad(self, omega, Y, weights, d_eps, d_gamma):
+        return nsf_eig_grad(self.handle, omega, Y, weights, d_eps, d_gamma)

@@ -1,0 +1,318 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: basis and A_r / B_r matvecs <= 1e-12 relative (max-abs error over
+max-abs value), CG true residual <= 10 x rtol, eigenvalues <= 1e-10 relative
+with residuals eta <= 1e-8 (these tolerances follow from FP64 FFTs of length
+<= 128, whose error grows like eps log n, and from the quadratic accuracy of
+Rayleigh quotients).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import basis, grad, medium, nfgep, yee
+from paper_1402_6297_amd import media, nsf
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(x, ref):
+    return np.abs(x - ref).max() / np.abs(ref).max()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+BASIS_CASES = [
+    ((4, 4, 4), (0.1, 0.2, 0.3)),
+    ((3, 4, 5), (0.25, 0.5, 0.1)),
+    ((2, 2, 2), (0.5, 0.0, 0.0)),
+    ((16, 16, 16), (0.1, 0.2, 0.3)),
+    ((6, 10, 12), (0.5, 0.5, 0.5)),
+    ((48, 16, 20), (0.0, 0.3, 0.0)),
+    ((50, 8, 6), (0.2, 0.0, 0.45)),
+]
+
+
+@pytest.mark.parametrize("grid,k", BASIS_CASES)
+def test_basis_applies_match_oracle(grid, k):
+    n = grid[0] * grid[1] * grid[2]
+    y = media.random_vector(2 * n, 1)
+    x = media.random_vector(3 * n, 2)
+    with nsf.Plan(grid, k) as P:
+        out3 = torch.empty(3 * n, dtype=torch.complex128, device="cuda")
+        out2 = torch.empty(2 * n, dtype=torch.complex128, device="cuda")
+        P.Pr(dev(y), out3)
+        assert rel(host(out3), basis.apply_Pr(y, grid, k)) < 1e-12
+        P.Qr(dev(y), out3)
+        assert rel(host(out3), basis.apply_Qr(y, grid, k)) < 1e-12
+        P.PrH(dev(x), out2)
+        assert rel(host(out2), basis.apply_PrH(x, grid, k)) < 1e-12
+        P.QrH(dev(x), out2)
+        assert rel(host(out2), basis.apply_QrH(x, grid, k)) < 1e-12
+
+
+def _medium(kind, grid):
+    n1, n2, n3 = grid
+    if kind == "chiral":
+        eps, gam = media.sphere_chiral(n1, n2, n3, radius=0.3)
+        return eps, gam, medium.tensors_chiral(eps, gam), None
+    if kind == "noise":
+        eps, gam = media.noise_chiral(n1, n2, n3, sigma_vox=1.0, seed=3)
+        return eps, gam, medium.tensors_chiral(eps, gam), None
+    pair = {"pseudo_xy": (0, 1), "pseudo_xz": (0, 2), "pseudo_yz": (1, 2)}[kind]
+    eps, gam = media.rods_pseudochiral(n1, n2, n3, radius=0.3)
+    return eps, gam, medium.tensors_pseudochiral(eps, gam, pair), pair
+
+
+def _set(P, eps, gam, pair):
+    if pair is None:
+        P.set_chiral(eps, gam)
+    else:
+        P.set_pseudochiral(pair[0], pair[1], eps, gam)
+
+
+AR_CASES = [
+    ((4, 4, 4), (0.1, 0.2, 0.3), "chiral"),
+    ((3, 4, 5), (0.25, 0.5, 0.1), "pseudo_xz"),
+    ((2, 4, 2), (0.5, 0.1, 0.0), "noise"),
+    ((16, 16, 16), (0.1, 0.2, 0.3), "chiral"),
+    ((16, 12, 10), (0.3, 0.1, 0.2), "pseudo_xy"),
+    ((8, 20, 6), (0.4, 0.4, 0.1), "pseudo_yz"),
+    ((48, 16, 20), (0.0, 0.3, 0.0), "noise"),
+]
+
+
+@pytest.mark.parametrize("grid,k,kind", AR_CASES)
+def test_Ar_Br_match_oracle(grid, k, kind):
+    n = grid[0] * grid[1] * grid[2]
+    eps, gam, tens, pair = _medium(kind, grid)
+    u = media.random_vector(4 * n, 5)
+    with nsf.Plan(grid, k) as P:
+        _set(P, eps, gam, pair)
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        assert rel(host(out), nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+        P.Br(dev(u), out)
+        assert rel(host(out), nfgep.apply_Br(u, grid, k)) < 1e-14
+        ud = dev(u)
+        P.Br(ud, ud)  # in place is allowed
+        assert rel(host(ud), nfgep.apply_Br(u, grid, k)) < 1e-14
+
+
+@pytest.mark.parametrize("grid,k", [((64, 64, 64), (0.25, 0.0, 0.0)), ((128, 128, 128), (0.1, 0.2, 0.3))])
+def test_Ar_full_size(grid, k):
+    """A_r at the benchmark sizes against the oracle's numpy-FFT route."""
+    n = grid[0] * grid[1] * grid[2]
+    eps, gam = media.sphere_chiral(grid[0])
+    tens = medium.tensors_chiral(eps, gam)
+    u = media.random_vector(4 * n, 11)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        got = host(out)
+    ref = nfgep.apply_Ar(u, grid, k, tens)
+    assert rel(got, ref) < 1e-12
+
+
+def test_Ar_rods_128():
+    grid, k = (128, 128, 128), (0.1, 0.2, 0.3)
+    n = 128 ** 3
+    eps, gam = media.rods_pseudochiral(128)
+    tens = medium.tensors_pseudochiral(eps, gam, (0, 1))
+    u = media.random_vector(4 * n, 12)
+    with nsf.Plan(grid, k) as P:
+        P.set_pseudochiral(0, 1, eps, gam)
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        got = host(out)
+    assert rel(got, nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+
+
+def test_Ar_is_deterministic():
+    grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
+    n = 4096
+    eps, gam = media.sphere_chiral(16)
+    u = dev(media.random_vector(4 * n, 3))
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        a = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        P.Ar(u, a)
+        P.Ar(u, b)
+        assert torch.equal(a, b)
+
+
+def test_medium_from_device_pointers():
+    grid, k = (8, 8, 8), (0.1, 0.2, 0.3)
+    n = 512
+    eps, gam = media.sphere_chiral(8)
+    tens = medium.tensors_chiral(eps, gam)
+    u = media.random_vector(4 * n, 4)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(dev(eps.ravel()), dev(gam.ravel()))
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        assert rel(host(out), nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+        bad = gam.ravel().copy()
+        bad[3] = 5.0
+        with pytest.raises(nsf.NsfError) as e:
+            P.set_chiral(dev(eps.ravel()), dev(bad))
+        assert e.value.status == nsf.NSF_E_NOT_HHPD
+
+
+def test_apply_Ar_without_medium_is_an_error():
+    with nsf.Plan((4, 4, 4), (0.1, 0.2, 0.3)) as P:
+        u = torch.zeros(256, dtype=torch.complex128, device="cuda")
+        with pytest.raises(nsf.NsfError) as e:
+            P.Ar(u, torch.empty_like(u))
+        assert e.value.status == nsf.NSF_E_STATE
+
+
+# ----------------------------------------------------------------------- CG
+
+@pytest.mark.parametrize("grid,kind", [((16, 16, 16), "chiral"), ((12, 10, 8), "pseudo_xy")])
+def test_cg_true_residual(grid, kind):
+    k = (0.1, 0.2, 0.3)
+    n = grid[0] * grid[1] * grid[2]
+    eps, gam, tens, pair = _medium(kind, grid)
+    b = media.random_vector(4 * n, 9)
+    with nsf.Plan(grid, k) as P:
+        _set(P, eps, gam, pair)
+        x = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        st, it, relres = P.cg(dev(b), x, rtol=1e-12, maxit=2000)
+        assert st == nsf.NSF_OK and relres <= 1e-12
+        xh = host(x)
+    r = b - nfgep.apply_Ar(xh, grid, k, tens)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-11
+    x_or, it_or, _ = nfgep.cg(lambda v: nfgep.apply_Ar(v, grid, k, tens), b, rtol=1e-12)
+    assert abs(it - it_or) <= 2
+    assert rel(xh, x_or) < 1e-9
+
+
+def test_cg_air_one_iteration_and_caps():
+    grid, k = (8, 8, 8), (0.1, 0.2, 0.3)
+    n = 512
+    eps, gam = media.homogeneous(8, eps=1.0, gamma=0.0)
+    b = dev(media.random_vector(4 * n, 1))
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        x = torch.empty_like(b)
+        st, it, relres = P.cg(b, x, rtol=1e-12)
+        assert st == nsf.NSF_OK and it == 1
+        assert rel(host(x), host(b)) < 1e-13  # A_r = I for air
+        # iteration cap -> NOT_CONVERGED (returned, not raised)
+        eps, gam = media.sphere_chiral(8)
+        P.set_chiral(eps, gam)
+        st, it, relres = P.cg(b, x, rtol=1e-14, maxit=1)
+        assert st == nsf.NSF_NOT_CONVERGED and it == 1
+        z = torch.zeros_like(b)
+        st, it, relres = P.cg(z, x, rtol=1e-12)
+        assert st == nsf.NSF_OK and it == 0 and float(x.abs().max()) == 0.0
+
+
+# --------------------------------------------------------------- eigensolver
+
+def test_eigs_match_dense_gep_4():
+    grid, k = (4, 4, 4), (0.1, 0.2, 0.3)
+    eps, gam = media.sphere_chiral(4)
+    tens = medium.tensors_chiral(eps, gam)
+    ref = nfgep.positive_smallest(nfgep.gep_dense(grid, k, tens), 10, 1e-8)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        Y = torch.empty(4 * 64 * 10, dtype=torch.complex128, device="cuda")
+        st, om, res, stats = P.eigs(10, res_tol=1e-10, cg_rtol=1e-12, Y=Y)
+        Yh = host(Y).reshape(10, 4 * 64)
+    assert st == nsf.NSF_OK
+    assert np.abs(om - ref).max() < 1e-10 * ref.max()
+    assert res.max() <= 1e-10
+    for j in range(3):  # eigenvectors are eigenvectors of the oracle's pencil
+        assert nfgep.pencil_residual(Yh[j], 1 / om[j], grid, k, tens) < 1e-9
+
+
+def test_eigs_config1_golden():
+    g = json.load(open(os.path.join(HERE, "golden", "config1_16.json")))
+    grid, k = tuple(g["grid"]), tuple(g["k"])
+    eps, gam = media.sphere_chiral(16)
+    ref = np.array(g["omega"])
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st, om, res, stats = P.eigs(10, res_tol=1e-8, cg_rtol=1e-10, seed=0)
+    assert st == nsf.NSF_OK
+    assert res.max() <= 1e-8
+    assert np.abs(om - ref).max() <= 1e-10 * ref.max()
+
+
+def test_eigs_homogeneous_closed_form_16():
+    grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
+    eps0, g0 = 13.0, 0.5
+    eps, gam = media.homogeneous(16, eps=eps0, gamma=g0)
+    L1, L2, L3 = yee.lambdas(grid, k)
+    s2 = np.abs(L1) ** 2 + np.abs(L2) ** 2 + np.abs(L3) ** 2
+    c = L1 ** 2 + L2 ** 2 + L3 ** 2
+    Phi = eps0 - g0 ** 2
+    disc = np.sqrt(eps0 * (s2 - c.real) ** 2 + Phi * c.imag ** 2)
+    cf = np.sort(np.sqrt(np.concatenate([eps0 * s2 - g0 ** 2 * c.real + g0 * disc,
+                                         eps0 * s2 - g0 ** 2 * c.real - g0 * disc]) / Phi ** 2))[:6]
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st, om, res, stats = P.eigs(6, res_tol=1e-9, cg_rtol=1e-11)
+    assert st == nsf.NSF_OK
+    assert np.abs(om - cf).max() <= 1e-10 * cf.max()
+
+
+def test_eigs_alpha_beta_invariance_and_pseudochiral():
+    grid, k = (8, 8, 8), (0.1, 0.2, 0.3)
+    eps, gam = media.rods_pseudochiral(8, radius=0.3)
+    out = []
+    for ab in ((-1.0, 2.0), (2.0, -3.0)):
+        with nsf.Plan(grid, k, alpha=ab[0], beta=ab[1]) as P:
+            P.set_pseudochiral(0, 1, eps, gam)
+            st, om, res, stats = P.eigs(6, res_tol=1e-9, cg_rtol=1e-11)
+            assert st == nsf.NSF_OK
+            out.append(om)
+    assert np.abs(out[0] - out[1]).max() <= 1e-10 * out[0].max()
+    tens = medium.tensors_pseudochiral(eps, gam, (0, 1))
+    ref = nfgep.gep_shift_invert(grid, k, tens, nev=6)
+    assert np.abs(out[0] - ref).max() <= 1e-10 * ref.max()
+
+
+# --------------------------------------------------------------- gradient
+
+def test_gradient_matches_oracle_4():
+    grid, k = (4, 4, 4), (0.1, 0.2, 0.3)
+    eps, gam = media.noise_chiral(4, sigma_vox=1.0, seed=4)
+    om_ref, de_ref, dg_ref = grad.chiral_eigs_and_grads(grid, k, eps, gam, 3)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        Y = torch.empty(4 * 64 * 3, dtype=torch.complex128, device="cuda")
+        st, om, res, stats = P.eigs(3, res_tol=1e-11, cg_rtol=1e-13, Y=Y)
+        assert st == nsf.NSF_OK
+        w = np.array([1.0, 0.5, -2.0])
+        de = torch.empty(64, dtype=torch.float64, device="cuda")
+        dg = torch.empty_like(de)
+        P.eig_grad(om, Y, w, de, dg)
+        de, dg = host(de), host(dg)
+    assert np.abs(om - om_ref).max() < 1e-10 * om_ref.max()
+    ref_e = (w[:, None] * de_ref).sum(axis=0)
+    ref_g = (w[:, None] * dg_ref).sum(axis=0)
+    assert rel(de, ref_e) < 1e-8
+    assert rel(dg, ref_g) < 1e-8
