@@ -142,6 +142,17 @@ int nsf_apply_QrH(nsf_plan plan, const nsf_c128* x3n, nsf_c128* y2n);
  */
 int nsf_apply_Ar(nsf_plan plan, const nsf_c128* u4n, nsf_c128* out4n);
 
+/*
+ * Timing of the A_r apply (tracing aid): runs `reps` applies of u -> out with a
+ * HIP event between consecutive kernels on the plan's stream, then `reps`
+ * applies back to back.  ms_pass[i] (i < min(*npass, max_pass)) receives the
+ * average milliseconds of kernel i of one apply, *npass the number of kernels,
+ * *ms_apply the average milliseconds of a whole apply without the events.
+ * Device vectors as nsf_apply_Ar; host outputs nullable.  Synchronises.
+ */
+int nsf_profile_Ar(nsf_plan plan, const nsf_c128* u4n, nsf_c128* out4n, int reps,
+                   double* ms_pass, int max_pass, int* npass, double* ms_apply);
+
 /* out = B_r u (Thm 4.2).  Device 4n vectors, may alias.  Asynchronous. */
 int nsf_apply_Br(nsf_plan plan, const nsf_c128* u4n, nsf_c128* out4n);
 

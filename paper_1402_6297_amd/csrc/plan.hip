@@ -380,6 +380,59 @@ int nsf_apply_Ar(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n) {
                       nullptr);
 }
 
+int nsf_profile_Ar(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n, int reps, double* ms_pass,
+                   int max_pass, int* npass, double* ms_apply) {
+  if (!p || !u4n || !out4n || reps < 1) return set_error(p, NSF_E_ARG, "bad argument");
+  if (p->medium_kind == kMedNone) return set_error(p, NSF_E_STATE, "no medium set");
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  const Geom& g = p->geom;
+  hipStream_t s = p->stream;
+  double2* F = p->d_fields;
+  const double2* u = reinterpret_cast<const double2*>(u4n);
+  double2* out = reinterpret_cast<double2*>(out4n);
+  constexpr int kPasses = 5;
+  hipEvent_t ev[kPasses + 1];
+  for (auto& e : ev) NSF_HIP(p, hipEventCreate(&e));
+  double acc[kPasses] = {0, 0, 0, 0, 0};
+  for (int r = 0; r < reps; ++r) {
+    NSF_HIP(p, hipEventRecord(ev[0], s));
+    NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartBoth, u, F, nullptr, s));
+    NSF_HIP(p, hipEventRecord(ev[1], s));
+    NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 6, F, 0, 0, nullptr, s));
+    NSF_HIP(p, hipEventRecord(ev[2], s));
+    NSF_HIP(p, launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), F, nullptr, s));
+    NSF_HIP(p, hipEventRecord(ev[3], s));
+    NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, -1, 6, F, 0, 0, nullptr, s));
+    NSF_HIP(p, hipEventRecord(ev[4], s));
+    NSF_HIP(p, launch_x_fwd_proj(g, p->ax[0], p->tabs, kPartBoth, F, out, nullptr, s));
+    NSF_HIP(p, hipEventRecord(ev[5], s));
+    NSF_HIP(p, hipEventSynchronize(ev[5]));
+    for (int i = 0; i < kPasses; ++i) {
+      float ms = 0;
+      NSF_HIP(p, hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+      acc[i] += ms;
+    }
+  }
+  if (npass) *npass = kPasses;
+  if (ms_pass)
+    for (int i = 0; i < kPasses && i < max_pass; ++i) ms_pass[i] = acc[i] / reps;
+  if (ms_apply) {
+    NSF_HIP(p, hipEventRecord(ev[0], s));
+    for (int r = 0; r < reps; ++r) {
+      rc = apply_Ar_dev(p, u, out, nullptr);
+      if (rc) return rc;
+    }
+    NSF_HIP(p, hipEventRecord(ev[1], s));
+    NSF_HIP(p, hipEventSynchronize(ev[1]));
+    float ms = 0;
+    NSF_HIP(p, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    *ms_apply = ms / reps;
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  return NSF_OK;
+}
+
 int nsf_apply_Br(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n) {
   if (!p || !u4n || !out4n) return set_error(p, NSF_E_ARG, "NULL argument");
   int rc = ensure_device(p);

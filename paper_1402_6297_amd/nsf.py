@@ -32,7 +32,7 @@ EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query",
     "nsf_set_medium_chiral", "nsf_set_medium_pseudochiral",
     "nsf_apply_Pr", "nsf_apply_Qr", "nsf_apply_PrH", "nsf_apply_QrH",
-    "nsf_apply_Ar", "nsf_apply_Br", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
+    "nsf_apply_Ar", "nsf_apply_Br", "nsf_profile_Ar", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
     "nsf_hermitian_eig", "nsf_status_string", "nsf_last_error",
 ]
 
@@ -78,6 +78,7 @@ def lib():
         "nsf_apply_QrH": (I, [P, VP, VP]),
         "nsf_apply_Ar": (I, [P, VP, VP]),
         "nsf_apply_Br": (I, [P, VP, VP]),
+        "nsf_profile_Ar": (I, [P, VP, VP, I, DP, I, C.POINTER(I), DP]),
         "nsf_cg_solve": (I, [P, VP, VP, D, I, C.POINTER(I), DP]),
         "nsf_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, VP, DP, C.POINTER(nsf_stats)]),
         "nsf_eig_grad": (I, [P, I, DP, VP, DP, VP, VP]),
@@ -196,6 +197,16 @@ def nsf_apply_Br(plan, u4n, out4n):
     return _apply("nsf_apply_Br", plan, u4n, out4n)
 
 
+def nsf_profile_Ar(plan, u4n, out4n, reps=20):
+    """Returns (per-kernel average ms list, whole-apply average ms)."""
+    ms = (C.c_double * 16)()
+    npass = C.c_int()
+    whole = C.c_double()
+    _check(lib().nsf_profile_Ar(plan, _dptr(u4n, "c128"), _dptr(out4n, "c128"), int(reps), ms, 16,
+                                C.byref(npass), C.byref(whole)), plan)
+    return [ms[i] for i in range(npass.value)], whole.value
+
+
 def nsf_cg_solve(plan, b, x, rtol=1e-10, maxit=10000):
     it, rel = C.c_int(), C.c_double()
     st = _check(lib().nsf_cg_solve(plan, _dptr(b, "c128"), _dptr(x, "c128"), float(rtol), int(maxit),
@@ -282,6 +293,9 @@ class Plan:
 
     def Ar(self, u, out):
         return nsf_apply_Ar(self.handle, u, out)
+
+    def profile_Ar(self, u, out, reps=20):
+        return nsf_profile_Ar(self.handle, u, out, reps)
 
     def Br(self, u, out):
         return nsf_apply_Br(self.handle, u, out)
