@@ -89,6 +89,20 @@ int nsf_plan_create(nsf_plan* out, int n1, int n2, int n3, double a,
                     const double k[3], double alpha, double beta,
                     void* hip_stream);
 
+/* Tuning options of a plan (nsf_plan_set_option). */
+enum {
+  NSF_OPT_FFT_PATH = 1,  /* 0: register-resident passes where the axis length
+                            allows them (default), 1: generic LDS-staged passes */
+  NSF_OPT_MID_COLS = 2   /* pencils per workgroup of the fused z pass: 1..16,
+                            power of two (default 4)                          */
+};
+
+/*
+ * Set a tuning option.  Options change speed, never results beyond rounding.
+ * Host-only.  NSF_E_ARG for an unknown option or value.
+ */
+int nsf_plan_set_option(nsf_plan plan, int option, int value);
+
 /* Free the plan and all device memory it owns.  NULL is accepted. */
 void nsf_plan_destroy(nsf_plan plan);
 

@@ -1,0 +1,495 @@
+// Register-resident pencil passes for axis lengths N = N1 * N2 (the fast path).
+//
+// Each length-N transform of a pencil is split as
+//   X[k1 + N1 k2] = sum_{n2} W_N^{n2 k1} [ sum_{n1} x[n2 + N2 n1] W_{N1}^{n1 k1} ] W_{N2}^{n2 k2}:
+// N2 threads per pencil; thread n2 loads its N1 points straight from global
+// memory, does the N1-point DFT in registers and the twiddle, one LDS
+// exchange hands every thread the N2 values of its k1's, and the N2-point
+// DFTs write natural-order results straight back to global memory.  Compared
+// with staging every radix stage through LDS this needs one exchange per
+// transform and few registers, so several workgroups share a CU and hide HBM
+// latency.  The fused steps (basis synthesis, per-voxel middle factor,
+// projection, twist) are the same as in the generic passes.
+#include "nsf_internal.h"
+#include "fft_common.h"
+
+namespace nsf {
+namespace {
+
+// ----------------------------------------------------------- two-level core
+// Step 1 for one thread: v[n1] = x[n2 + N2 n1] -> B[k1] * W_N^{S n2 k1}.
+template <int N1, int N2, int S>
+__device__ __forceinline__ void step1(double2 (&v)[N1], int n2, const double2* twl) {
+  reg_dft<N1, S>(v);
+  if (n2 > 0) {
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      double2 t = twl[n2 * k1];
+      if (S < 0) t = cconj(t);
+      v[k1] = cmul(v[k1], t);
+    }
+  }
+}
+
+template <int N1, int N2>
+struct Split {
+  static constexpr int N = N1 * N2;
+  static constexpr int D = (N1 + N2 - 1) / N2;  // step-2 transforms per thread
+};
+
+// ------------------------------------------------------------ y / z passes
+// P pencils (consecutive x) per workgroup, N2 threads per pencil, lane order
+// p fastest.  LDS tile[(e) * P + p], e = n2 + N2 k1.
+template <int N1, int N2, int S>
+__global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2* __restrict__ fld,
+                                             int P, int post_twist, int pre_twist, const int* skip) {
+  if (skip && *skip) return;
+  constexpr int N = N1 * N2;
+  constexpr int D = Split<N1, N2>::D;
+  extern __shared__ double2 sm[];
+  double2* twl = sm;
+  double2* tile = sm + N;
+  const int twoff = (axis == 1) ? g.n1 : g.n1 + g.n2;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = t.tw[twoff + i];
+  const int p = threadIdx.x % P;
+  const int n2 = threadIdx.x / P;
+  const int groups1 = g.n1 / P;
+  const int i1_0 = (int)(blockIdx.x % groups1) * P;
+  const int io = (int)(blockIdx.x / groups1);
+  long long base, stride;
+  if (axis == 1) {
+    base = (long long)io * g.n1 * g.n2 + i1_0;
+    stride = g.n1;
+  } else {
+    base = (long long)io * g.n1 + i1_0;
+    stride = (long long)g.n1 * g.n2;
+  }
+  double2* F = fld + (long long)blockIdx.y * g.n + base + p;
+  const double rs = 1.0 / sqrt((double)g.n);
+  double2 v[N1];
+#pragma unroll
+  for (int n1 = 0; n1 < N1; ++n1) {
+    const int j = n2 + N2 * n1;
+    double2 x = F[j * stride];
+    if (pre_twist) x = cscale(cmulc(twist_at(t.twist, g, i1_0 + p, io, j), x), rs);
+    v[n1] = x;
+  }
+  __syncthreads();  // twiddle table ready
+  step1<N1, N2, S>(v, n2, twl);
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) tile[(n2 + N2 * k1) * P + p] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+      double2 u[N2];
+#pragma unroll
+      for (int m = 0; m < N2; ++m) u[m] = tile[(m + N2 * k1) * P + p];
+      reg_dft<N2, S>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int j = k1 + N1 * k2;
+        double2 x = u[k2];
+        if (post_twist) x = cscale(cmul(twist_at(t.twist, g, i1_0 + p, io, j), x), rs);
+        F[j * stride] = x;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------ z pass with medium
+template <int N1, int N2>
+__global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med,
+                                                double2* __restrict__ fld, int P, const int* skip) {
+  if (skip && *skip) return;
+  constexpr int N = N1 * N2;
+  constexpr int D = Split<N1, N2>::D;
+  extern __shared__ double2 sm[];
+  double2* twl = sm;
+  double2* tile = sm + N;  // [(c * N + e) * P + p]
+  const int twoff = g.n1 + g.n2;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = t.tw[twoff + i];
+  const int p = threadIdx.x % P;
+  const int n2 = (threadIdx.x / P) % N2;
+  const int c = threadIdx.x / (P * N2);
+  const int groups1 = g.n1 / P;
+  const int i1_0 = (int)(blockIdx.x % groups1) * P;
+  const int i2 = (int)(blockIdx.x / groups1);
+  const long long base = (long long)i2 * g.n1 + i1_0;
+  const long long stride = (long long)g.n1 * g.n2;
+  const long long n = g.n;
+  double2* F = fld + c * n + base + p;
+  double2* T = tile + c * N * P + p;
+  double2 v[N1];
+#pragma unroll
+  for (int n1 = 0; n1 < N1; ++n1) v[n1] = F[(n2 + N2 * n1) * stride];
+  __syncthreads();
+  // inverse z
+  step1<N1, N2, +1>(v, n2, twl);
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) T[(n2 + N2 * k1) * P] = v[k1];
+  __syncthreads();
+  double2 out[D][N2];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+#pragma unroll
+      for (int m = 0; m < N2; ++m) out[d][m] = T[(m + N2 * k1) * P];
+      reg_dft<N2, +1>(out[d]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) T[(k1 + N1 * k2) * P] = out[d][k2];
+    }
+  }
+  __syncthreads();
+  // per-voxel middle factor (times 1/n)
+  const double inv_n = 1.0 / (double)n;
+  for (int vx = threadIdx.x; vx < P * N; vx += blockDim.x) {
+    const int pp = vx % P, j = vx / P;
+    double2 E[3], H[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      E[cc] = tile[(cc * N + j) * P + pp];
+      H[cc] = tile[((3 + cc) * N + j) * P + pp];
+    }
+    medium_apply(med, med.eg[base + j * stride + pp], inv_n, E, H);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      tile[(cc * N + j) * P + pp] = E[cc];
+      tile[((3 + cc) * N + j) * P + pp] = H[cc];
+    }
+  }
+  __syncthreads();
+  // forward z
+#pragma unroll
+  for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[(n2 + N2 * n1) * P];
+  __syncthreads();
+  step1<N1, N2, -1>(v, n2, twl);
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) T[(n2 + N2 * k1) * P] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+      double2 u[N2];
+#pragma unroll
+      for (int m = 0; m < N2; ++m) u[m] = T[(m + N2 * k1) * P];
+      reg_dft<N2, -1>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) F[(k1 + N1 * k2) * stride] = u[k2];
+    }
+  }
+}
+
+// ------------------------------------------------------------- x passes
+// R rows per workgroup; LDS tile[(c * R + r) * (N + 1) + e].
+template <int N1, int N2, int PART>
+__global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const double2* __restrict__ y,
+                                                      double2* __restrict__ fld, int R,
+                                                      const int* skip) {
+  if (skip && *skip) return;
+  constexpr int N = N1 * N2;
+  constexpr int NP = N + 1;
+  constexpr int D = Split<N1, N2>::D;
+  constexpr int F = (PART == kPartBoth) ? 6 : 3;
+  extern __shared__ double2 sm[];
+  double2* twl = sm;
+  double2* tile = sm + N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = t.tw[i];
+  const long long rows = (long long)g.n2 * g.n3;
+  const long long row0 = (long long)blockIdx.x * R;
+  const long long n = g.n;
+  // synthesis of the coefficient fields, one frequency per thread and step
+  for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
+    const int r = e / N, i1 = e - r * N;
+    const long long row = row0 + r;
+    if (row >= rows) continue;
+    const int i2 = (int)(row % g.n2), i3 = (int)(row / g.n2);
+    const long long f = row * N + i1;
+    Basis B;
+    basis_at(t.lam, g, i1, i2, i3, B);
+    if (PART == kPartBoth || PART == kPartP) {
+      const double2 ya = y[f], yb = y[n + f];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        tile[(cc * R + r) * NP + i1] = csub(cmulc(B.pi1[cc], yb), cmulc(B.pi2[cc], ya));
+    }
+    if (PART == kPartBoth || PART == kPartQ) {
+      const long long o = (PART == kPartBoth) ? 2 * n : 0;
+      const int cb = (PART == kPartBoth) ? 3 : 0;
+      const double2 yc = y[o + f], yd = y[o + n + f];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        tile[((cb + cc) * R + r) * NP + i1] = cadd(cmul(B.pi1[cc], yc), cmul(B.pi2[cc], yd));
+    }
+  }
+  __syncthreads();
+  const int n2 = threadIdx.x % N2;
+  const int r = (threadIdx.x / N2) % R;
+  const int c = threadIdx.x / (N2 * R);
+  const bool active = c < F && row0 + r < rows;
+  double2* T = tile + (c * R + r) * NP;
+  double2 v[N1];
+  if (active) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[n2 + N2 * n1];
+    step1<N1, N2, +1>(v, n2, twl);
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) T[n2 + N2 * k1] = v[k1];
+  }
+  __syncthreads();
+  if (!active) return;
+  double2* out = fld + c * n + (row0 + r) * N;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+      double2 u[N2];
+#pragma unroll
+      for (int m = 0; m < N2; ++m) u[m] = T[m + N2 * k1];
+      reg_dft<N2, +1>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) out[k1 + N1 * k2] = u[k2];
+    }
+  }
+}
+
+template <int N1, int N2, int PART>
+__global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
+                                                     double2* __restrict__ out, int R,
+                                                     const int* skip) {
+  if (skip && *skip) return;
+  constexpr int N = N1 * N2;
+  constexpr int NP = N + 1;
+  constexpr int D = Split<N1, N2>::D;
+  constexpr int F = (PART == kPartBoth) ? 6 : 3;
+  extern __shared__ double2 sm[];
+  double2* twl = sm;
+  double2* tile = sm + N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = t.tw[i];
+  const long long rows = (long long)g.n2 * g.n3;
+  const long long row0 = (long long)blockIdx.x * R;
+  const long long n = g.n;
+  const int n2 = threadIdx.x % N2;
+  const int r = (threadIdx.x / N2) % R;
+  const int c = threadIdx.x / (N2 * R);
+  const bool active = c < F && row0 + r < rows;
+  double2* T = tile + (c * R + r) * NP;
+  double2 v[N1];
+  if (active) {
+    const double2* src = fld + c * n + (row0 + r) * N;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = src[n2 + N2 * n1];
+  }
+  __syncthreads();
+  if (active) {
+    step1<N1, N2, -1>(v, n2, twl);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) T[n2 + N2 * k1] = v[k1];
+  }
+  __syncthreads();
+  double2 res[D][N2];
+  if (active) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int k1 = n2 + d * N2;
+      if (k1 < N1) {
+#pragma unroll
+        for (int m = 0; m < N2; ++m) res[d][m] = T[m + N2 * k1];
+        reg_dft<N2, -1>(res[d]);
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int k1 = n2 + d * N2;
+      if (k1 < N1) {
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) T[k1 + N1 * k2] = res[d][k2];
+      }
+    }
+  }
+  __syncthreads();
+  // projection, one frequency per thread and step
+  for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
+    const int rr = e / N, i1 = e - rr * N;
+    const long long row = row0 + rr;
+    if (row >= rows) continue;
+    const int i2 = (int)(row % g.n2), i3 = (int)(row / g.n2);
+    const long long f = row * N + i1;
+    Basis B;
+    basis_at(t.lam, g, i1, i2, i3, B);
+    if (PART == kPartBoth || PART == kPartP) {
+      double2 oa = make_double2(0, 0), ob = make_double2(0, 0);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const double2 o = tile[(cc * R + rr) * NP + i1];
+        oa = csub(oa, cmul(B.pi2[cc], o));
+        ob = cadd(ob, cmul(B.pi1[cc], o));
+      }
+      out[f] = oa;
+      out[n + f] = ob;
+    }
+    if (PART == kPartBoth || PART == kPartQ) {
+      const long long o0 = (PART == kPartBoth) ? 2 * n : 0;
+      const int cb = (PART == kPartBoth) ? 3 : 0;
+      double2 oc = make_double2(0, 0), od = make_double2(0, 0);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const double2 o = tile[((cb + cc) * R + rr) * NP + i1];
+        oc = cadd(oc, cmulc(B.pi1[cc], o));
+        od = cadd(od, cmulc(B.pi2[cc], o));
+      }
+      out[o0 + f] = oc;
+      out[o0 + n + f] = od;
+    }
+  }
+}
+
+// ------------------------------------------------------------- dispatch
+struct FastCfg {
+  int N1, N2;
+};
+
+bool fast_cfg(int N, FastCfg& c) {
+  switch (N) {
+    case 128: c = {16, 8}; return true;
+    case 64: c = {8, 8}; return true;
+    case 32: c = {8, 4}; return true;
+    case 16: c = {4, 4}; return true;
+    case 256: c = {16, 16}; return true;
+    case 96: c = {16, 6}; return true;
+    case 48: c = {16, 3}; return true;
+    default: return false;
+  }
+}
+
+#define NSF_FAST_SWITCH(N, MACRO) \
+  switch (N) {                    \
+    case 128: MACRO(16, 8); break; \
+    case 64: MACRO(8, 8); break;   \
+    case 32: MACRO(8, 4); break;   \
+    case 16: MACRO(4, 4); break;   \
+    case 256: MACRO(16, 16); break; \
+    case 96: MACRO(16, 6); break;  \
+    case 48: MACRO(16, 3); break;  \
+    default: return hipErrorInvalidValue; \
+  }
+
+int pick_cols(int n1, int want) {
+  int P = 1;
+  while (P * 2 <= want && n1 % (P * 2) == 0) P *= 2;
+  return P;
+}
+
+}  // namespace
+
+bool fast_axis(int N) {
+  FastCfg c;
+  return fast_cfg(N, c);
+}
+
+hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int nf, double2* fld,
+                          int post_twist, int pre_twist, const int* skip, hipStream_t s) {
+  const int N = axis == 1 ? g.n2 : g.n3;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
+  const int P = pick_cols(g.n1, 256 / cfg.N2 < 16 ? 256 / cfg.N2 : 16);
+  const long long other = (axis == 1) ? g.n3 : g.n2;
+  const dim3 grid((unsigned)((g.n1 / P) * other), (unsigned)nf);
+  const dim3 block(P * cfg.N2);
+  const size_t lds = sizeof(double2) * (size_t)(N + N * P);
+#define L_YZ(A, B)                                                                                   \
+  if (dir > 0)                                                                                       \
+    hipLaunchKernelGGL((k_fyz<A, B, +1>), grid, block, lds, s, g, t, axis, fld, P, post_twist,       \
+                       pre_twist, skip);                                                             \
+  else                                                                                               \
+    hipLaunchKernelGGL((k_fyz<A, B, -1>), grid, block, lds, s, g, t, axis, fld, P, post_twist,       \
+                       pre_twist, skip);
+  NSF_FAST_SWITCH(N, L_YZ)
+#undef L_YZ
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
+                             int P_want, const int* skip, hipStream_t s) {
+  const int N = g.n3;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
+  int P = pick_cols(g.n1, P_want);
+  while (P > 1 && (6 * P * cfg.N2 > 384 || (size_t)(N + 6 * N * P) * 16 > 64 * 1024)) P /= 2;
+  if (6 * P * cfg.N2 > 384) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((g.n1 / P) * g.n2));
+  const dim3 block(6 * P * cfg.N2);
+  const size_t lds = sizeof(double2) * (size_t)(N + 6 * N * P);
+#define L_MID(A, B) hipLaunchKernelGGL((k_fz_mid<A, B>), grid, block, lds, s, g, t, med, fld, P, skip);
+  NSF_FAST_SWITCH(N, L_MID)
+#undef L_MID
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, const double2* y, double2* fld,
+                                   const int* skip, hipStream_t s) {
+  const int N = g.n1;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
+  const int F = part == kPartBoth ? 6 : 3;
+  int R = 4;
+  while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
+  if (F * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const long long rows = (long long)g.n2 * g.n3;
+  const dim3 grid((unsigned)((rows + R - 1) / R));
+  const dim3 block(F * R * cfg.N2);
+  const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+#define L_XI(A, B)                                                                                    \
+  if (part == kPartBoth)                                                                              \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth>), grid, block, lds, s, g, t, y, fld, R, skip); \
+  else if (part == kPartP)                                                                            \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartP>), grid, block, lds, s, g, t, y, fld, R, skip);    \
+  else                                                                                                \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartQ>), grid, block, lds, s, g, t, y, fld, R, skip);
+  NSF_FAST_SWITCH(N, L_XI)
+#undef L_XI
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld, double2* out,
+                                  const int* skip, hipStream_t s) {
+  const int N = g.n1;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
+  const int F = part == kPartBoth ? 6 : 3;
+  int R = 4;
+  while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
+  if (F * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const long long rows = (long long)g.n2 * g.n3;
+  const dim3 grid((unsigned)((rows + R - 1) / R));
+  const dim3 block(F * R * cfg.N2);
+  const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+#define L_XF(A, B)                                                                                     \
+  if (part == kPartBoth)                                                                               \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth>), grid, block, lds, s, g, t, fld, out, R, skip); \
+  else if (part == kPartP)                                                                             \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartP>), grid, block, lds, s, g, t, fld, out, R, skip);    \
+  else                                                                                                 \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartQ>), grid, block, lds, s, g, t, fld, out, R, skip);
+  NSF_FAST_SWITCH(N, L_XF)
+#undef L_XF
+  return hipGetLastError();
+}
+
+}  // namespace nsf

@@ -14,91 +14,10 @@
 // an LDS copy of exp(+2 pi i m / N), does the radix-R DFT and writes the
 // results back in autosorted order.
 #include "nsf_internal.h"
+#include "fft_common.h"
 
 namespace nsf {
 namespace {
-
-// ----------------------------------------------------------- small DFTs
-template <int S>
-__device__ inline double2 mul_si(double2 a) {  // (S i) * a
-  return S > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
-}
-
-template <int S>
-__device__ inline void dft2(double2* v) {
-  const double2 a = v[0], b = v[1];
-  v[0] = cadd(a, b);
-  v[1] = csub(a, b);
-}
-
-template <int S>
-__device__ inline void dft4(double2* v) {
-  const double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-  const double2 t2 = cadd(v[1], v[3]), t3 = mul_si<S>(csub(v[1], v[3]));
-  v[0] = cadd(t0, t2);
-  v[2] = csub(t0, t2);
-  v[1] = cadd(t1, t3);
-  v[3] = csub(t1, t3);
-}
-
-template <int S>
-__device__ inline void dft8(double2* v) {
-  double2 e[4] = {v[0], v[2], v[4], v[6]};
-  double2 o[4] = {v[1], v[3], v[5], v[7]};
-  dft4<S>(e);
-  dft4<S>(o);
-  constexpr double h = 0.70710678118654752440;
-  const double2 o1 = cmul(o[1], make_double2(h, S * h));
-  const double2 o2 = mul_si<S>(o[2]);
-  const double2 o3 = cmul(o[3], make_double2(-h, S * h));
-  v[0] = cadd(e[0], o[0]);
-  v[4] = csub(e[0], o[0]);
-  v[1] = cadd(e[1], o1);
-  v[5] = csub(e[1], o1);
-  v[2] = cadd(e[2], o2);
-  v[6] = csub(e[2], o2);
-  v[3] = cadd(e[3], o3);
-  v[7] = csub(e[3], o3);
-}
-
-template <int S>
-__device__ inline void dft3(double2* v) {
-  constexpr double c = 0.86602540378443864676;  // sin(2 pi / 3)
-  const double2 t = cadd(v[1], v[2]);
-  const double2 m = csub(v[0], cscale(t, 0.5));
-  const double2 d = mul_si<S>(cscale(csub(v[1], v[2]), c));
-  v[0] = cadd(v[0], t);
-  v[1] = cadd(m, d);
-  v[2] = csub(m, d);
-}
-
-template <int S>
-__device__ inline void dft5(double2* v) {
-  constexpr double c1 = 0.30901699437494742410;   // cos(2 pi / 5)
-  constexpr double c2 = -0.80901699437494742410;  // cos(4 pi / 5)
-  constexpr double s1 = 0.95105651629515357212;   // sin(2 pi / 5)
-  constexpr double s2 = 0.58778525229247312917;   // sin(4 pi / 5)
-  const double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-  const double2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-  const double2 m1 = cadd(v[0], cadd(cscale(t1, c1), cscale(t2, c2)));
-  const double2 m2 = cadd(v[0], cadd(cscale(t1, c2), cscale(t2, c1)));
-  const double2 n1 = mul_si<S>(cadd(cscale(t3, s1), cscale(t4, s2)));
-  const double2 n2 = mul_si<S>(csub(cscale(t3, s2), cscale(t4, s1)));
-  v[0] = cadd(v[0], cadd(t1, t2));
-  v[1] = cadd(m1, n1);
-  v[4] = csub(m1, n1);
-  v[2] = cadd(m2, n2);
-  v[3] = csub(m2, n2);
-}
-
-template <int R, int S>
-__device__ inline void dft(double2* v) {
-  if constexpr (R == 2) dft2<S>(v);
-  else if constexpr (R == 3) dft3<S>(v);
-  else if constexpr (R == 4) dft4<S>(v);
-  else if constexpr (R == 5) dft5<S>(v);
-  else dft8<S>(v);
-}
 
 // One Stockham stage over a tile laid out as tile[(f*N + j)*P + p].
 // Butterfly b of a pencil reads points b + r*N/R; after the DFT its outputs
@@ -162,45 +81,6 @@ __device__ void tile_fft(double2* tile, const double2* tw, int F, int P, const A
     }
     Ns *= R;
   }
-}
-
-// ---------------------------------------------------------------- basis
-// Per-frequency singular-vector blocks (Thm 2.5): with lambda = (l1,l2,l3),
-// p = a x lambda (a column of Lambda_p, Lemma 2.2), sigma = ||lambda||:
-//   pi2 = conj(p)/||p||,  pi1 = (conj(lambda) x p)/(sigma ||p||),
-// the unit-norm columns of Pi_2 and Pi_1 (Pi_1 is the projection of
-// (alpha, beta, 1) off lambda/sigma, normalised).
-struct Basis {
-  double2 pi1[3], pi2[3];
-};
-
-__device__ inline void basis_at(const double2* __restrict__ lam, const Geom& g, int i1, int i2,
-                                int i3, Basis& B) {
-  const double2 l1 = lam[i1], l2 = lam[g.n1 + i2], l3 = lam[g.n1 + g.n2 + i3];
-  const double al = g.alpha, be = g.beta;
-  // p = (beta l3 - l2, l1 - alpha l3, alpha l2 - beta l1)
-  const double2 p1 = csub(cscale(l3, be), l2);
-  const double2 p2 = csub(l1, cscale(l3, al));
-  const double2 p3 = csub(cscale(l2, al), cscale(l1, be));
-  const double pn2 = cabs2(p1) + cabs2(p2) + cabs2(p3);
-  const double s2 = cabs2(l1) + cabs2(l2) + cabs2(l3);
-  const double ip = 1.0 / sqrt(pn2);
-  const double iq = 1.0 / sqrt(s2 * pn2);
-  B.pi2[0] = cscale(cconj(p1), ip);
-  B.pi2[1] = cscale(cconj(p2), ip);
-  B.pi2[2] = cscale(cconj(p3), ip);
-  // conj(l) x p
-  const double2 q1 = csub(cmulc(l2, p3), cmulc(l3, p2));
-  const double2 q2 = csub(cmulc(l3, p1), cmulc(l1, p3));
-  const double2 q3 = csub(cmulc(l1, p2), cmulc(l2, p1));
-  B.pi1[0] = cscale(q1, iq);
-  B.pi1[1] = cscale(q2, iq);
-  B.pi1[2] = cscale(q3, iq);
-}
-
-__device__ inline double2 twist_at(const double2* __restrict__ tws, const Geom& g, int i1, int i2,
-                                   int i3) {
-  return cmul(cmul(tws[i1], tws[g.n1 + i2]), tws[g.n1 + g.n2 + i3]);
 }
 
 // ------------------------------------------------------------- x passes
@@ -375,43 +255,6 @@ __global__ __launch_bounds__(kThreads) void k_yz_pass(Geom g, AxisPlan ax, Table
       v = cscale(cmul(d, v), rs);
     }
     F[base + j * stride + p] = v;
-  }
-}
-
-// ---------------------------------------------------- z pass with medium
-// Per voxel, with E', H' the untwisted inverse transforms (times n) and the
-// 1/n normalisation folded in, the middle factor of A_r (Thm 4.2) maps
-//   o2 = Phi^{-1} (xi E' + H'),  o1 = zeta o2 + E'   (mu = 1).
-// Chiral (xi = i gamma, zeta = -i gamma, Phi = eps - gamma^2):
-//   o1 = (eps E' - i gamma H')/Phi,  o2 = (i gamma E' + H')/Phi.
-// Pseudochiral on axes (a, b): xi = i gamma (e_a e_b^T + e_b e_a^T),
-//   Phi = eps - gamma^2 on a and b, eps on the third axis o.
-__device__ inline void medium_apply(const MediumView& m, double2 eg, double inv_n, double2* E,
-                                    double2* H) {
-  const double eps = eg.x, gam = eg.y;
-  if (m.kind == kMedChiral) {
-    const double ip = inv_n / (eps - gam * gam);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double2 e = E[c], h = H[c];
-      const double2 ige = cmuli(cscale(e, gam));
-      const double2 igh = cmuli(cscale(h, gam));
-      E[c] = cscale(csub(cscale(e, eps), igh), ip);
-      H[c] = cscale(cadd(ige, h), ip);
-    }
-  } else {
-    const double ip = inv_n / (eps - gam * gam);
-    const int a = m.pa, b = m.pb, o = m.po;
-    const double2 Ea = E[a], Eb = E[b], Eo = E[o];
-    const double2 o2a = cscale(cadd(cmuli(cscale(Eb, gam)), H[a]), ip);
-    const double2 o2b = cscale(cadd(cmuli(cscale(Ea, gam)), H[b]), ip);
-    const double2 o2o = cscale(H[o], inv_n / eps);
-    E[a] = csub(cscale(Ea, inv_n), cmuli(cscale(o2b, gam)));
-    E[b] = csub(cscale(Eb, inv_n), cmuli(cscale(o2a, gam)));
-    E[o] = cscale(Eo, inv_n);
-    H[a] = o2a;
-    H[b] = o2b;
-    H[o] = o2o;
   }
 }
 

@@ -72,9 +72,9 @@ extern "C" int nsf_eig_grad(nsf_plan p, int nev, const double* omega_host, const
   double2* F = p->d_fields;
   for (int j = 0; j < nev; ++j) {
     const double2* y = reinterpret_cast<const double2*>(Y_dev) + (size_t)j * len;
-    NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartBoth, y, F, nullptr, s));
-    NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 6, F, 0, 0, nullptr, s));
-    NSF_HIP(p, launch_yz_pass(g, p->ax[2], p->tabs, 2, +1, 6, F, 1, 0, nullptr, s));
+    NSF_HIP(p, pass_x_inv(p, kPartBoth, y, F, nullptr));
+    NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, nullptr));
+    NSF_HIP(p, pass_yz(p, 2, +1, 6, F, 1, 0, nullptr));
     NSF_HIP(p, launch_grad_accum(g, p->d_medium, F, weights_host[j] * omega_host[j], d_eps_dev,
                                  d_gamma_dev, j == 0, s));
   }

@@ -100,6 +100,18 @@ hipError_t launch_x_fwd_proj(const Geom& g, const AxisPlan& ax, const Tables& t,
                              int part, const double2* fld, double2* out,
                              const int* skip, hipStream_t s);
 
+// Register-resident fast path for axis lengths with a two-level split
+// (16, 32, 48, 64, 96, 128, 256); same semantics as the generic launchers.
+bool fast_axis(int N);
+hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, const double2* y,
+                                   double2* fld, const int* skip, hipStream_t s);
+hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int nf, double2* fld,
+                          int post_twist, int pre_twist, const int* skip, hipStream_t s);
+hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
+                             int P_want, const int* skip, hipStream_t s);
+hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld,
+                                  double2* out, const int* skip, hipStream_t s);
+
 // out = B_r u (Thm 4.2): per frequency 1/sigma_f times i / -i block swaps.
 hipError_t launch_apply_Br(const Geom& g, const Tables& t, const double2* u, double2* out,
                            const int* skip, hipStream_t s);
@@ -203,6 +215,10 @@ struct nsf_plan_s {
   double2* d_basis = nullptr;  // V and AV
   size_t basis_vectors = 0;    // capacity of V (and of AV)
 
+  // options (nsf_plan_set_option)
+  int opt_generic_fft = 0;  // 1: always use the generic LDS-staged passes
+  int opt_mid_cols = 4;     // pencils per workgroup of the fused z pass
+
   std::string last_error;
 };
 
@@ -220,6 +236,12 @@ int set_error(nsf_plan p, int code, const std::string& msg);
 int hip_check(nsf_plan p, hipError_t e, const char* what);
 MediumView medium_view(nsf_plan p);
 int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip);
+// Pass dispatch (fast path when the axis allows it, else generic).
+hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, const int* skip);
+hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post_twist, int pre_twist,
+                   const int* skip);
+hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip);
+hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip);
 int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
                  double* relres, long long* matvecs);
 int ensure_basis(nsf_plan p, size_t vectors);

@@ -87,17 +87,46 @@ MediumView medium_view(nsf_plan p) {
   return m;
 }
 
+hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, const int* skip) {
+  const Geom& g = p->geom;
+  if (!p->opt_generic_fft && fast_axis(g.n1))
+    return launch_fast_x_inv_synth(g, p->tabs, part, y, fld, skip, p->stream);
+  return launch_x_inv_synth(g, p->ax[0], p->tabs, part, y, fld, skip, p->stream);
+}
+
+hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post_twist, int pre_twist,
+                   const int* skip) {
+  const Geom& g = p->geom;
+  if (!p->opt_generic_fft && fast_axis(axis == 1 ? g.n2 : g.n3))
+    return launch_fast_yz(g, p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
+  return launch_yz_pass(g, p->ax[axis], p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
+}
+
+hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip) {
+  const Geom& g = p->geom;
+  if (!p->opt_generic_fft && fast_axis(g.n3))
+    return launch_fast_z_mid(g, p->tabs, medium_view(p), fld, p->opt_mid_cols, skip, p->stream);
+  return launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), fld, skip, p->stream);
+}
+
+hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip) {
+  const Geom& g = p->geom;
+  if (!p->opt_generic_fft && fast_axis(g.n1))
+    return launch_fast_x_fwd_proj(g, p->tabs, part, fld, out, skip, p->stream);
+  return launch_x_fwd_proj(g, p->ax[0], p->tabs, part, fld, out, skip, p->stream);
+}
+
 // A_r u in five passes: [synthesis + inverse x] [inverse y]
 // [inverse z, middle factor, forward z] [forward y] [forward x + projection].
 int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip) {
   const Geom& g = p->geom;
   hipStream_t s = p->stream;
   double2* F = p->d_fields;
-  NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartBoth, u, F, skip, s));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 6, F, 0, 0, skip, s));
-  NSF_HIP(p, launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), F, skip, s));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, -1, 6, F, 0, 0, skip, s));
-  NSF_HIP(p, launch_x_fwd_proj(g, p->ax[0], p->tabs, kPartBoth, F, out, skip, s));
+  NSF_HIP(p, pass_x_inv(p, kPartBoth, u, F, skip));
+  NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, skip));
+  NSF_HIP(p, pass_z_mid(p, F, skip));
+  NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, skip));
+  NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, skip));
   return NSF_OK;
 }
 
@@ -242,6 +271,22 @@ void nsf_plan_destroy(nsf_plan p) {
   delete p;
 }
 
+int nsf_plan_set_option(nsf_plan p, int option, int value) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  switch (option) {
+    case NSF_OPT_FFT_PATH:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_FFT_PATH takes 0 or 1");
+      p->opt_generic_fft = value;
+      return NSF_OK;
+    case NSF_OPT_MID_COLS:
+      if (value < 1 || value > 16 || (value & (value - 1))) return set_error(p, NSF_E_ARG, "NSF_OPT_MID_COLS takes 1, 2, 4, 8 or 16");
+      p->opt_mid_cols = value;
+      return NSF_OK;
+    default:
+      return set_error(p, NSF_E_ARG, "unknown option");
+  }
+}
+
 int nsf_plan_query(nsf_plan p, long long* n, int* medium_kind, double* sigma_min, double* sigma_max) {
   if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
   if (n) *n = p->geom.n;
@@ -329,10 +374,9 @@ int nsf_apply_Pr(nsf_plan p, const nsf_c128* y2n, nsf_c128* x3n) {
   if (rc) return rc;
   const Geom& g = p->geom;
   auto* x = reinterpret_cast<double2*>(x3n);
-  NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartP, reinterpret_cast<const double2*>(y2n), x,
-                                nullptr, p->stream));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 3, x, 0, 0, nullptr, p->stream));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[2], p->tabs, 2, +1, 3, x, 1, 0, nullptr, p->stream));
+  NSF_HIP(p, pass_x_inv(p, kPartP, reinterpret_cast<const double2*>(y2n), x, nullptr));
+  NSF_HIP(p, pass_yz(p, 1, +1, 3, x, 0, 0, nullptr));
+  NSF_HIP(p, pass_yz(p, 2, +1, 3, x, 1, 0, nullptr));
   return NSF_OK;
 }
 
@@ -342,10 +386,9 @@ int nsf_apply_Qr(nsf_plan p, const nsf_c128* y2n, nsf_c128* x3n) {
   if (rc) return rc;
   const Geom& g = p->geom;
   auto* x = reinterpret_cast<double2*>(x3n);
-  NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartQ, reinterpret_cast<const double2*>(y2n), x,
-                                nullptr, p->stream));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 3, x, 0, 0, nullptr, p->stream));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[2], p->tabs, 2, +1, 3, x, 1, 0, nullptr, p->stream));
+  NSF_HIP(p, pass_x_inv(p, kPartQ, reinterpret_cast<const double2*>(y2n), x, nullptr));
+  NSF_HIP(p, pass_yz(p, 1, +1, 3, x, 0, 0, nullptr));
+  NSF_HIP(p, pass_yz(p, 2, +1, 3, x, 1, 0, nullptr));
   return NSF_OK;
 }
 
@@ -356,10 +399,9 @@ static int apply_adjoint(nsf_plan p, int part, const nsf_c128* x3n, nsf_c128* y2
   const Geom& g = p->geom;
   double2* F = p->d_fields;
   NSF_HIP(p, hipMemcpyAsync(F, x3n, sizeof(double2) * 3 * g.n, hipMemcpyDeviceToDevice, p->stream));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[2], p->tabs, 2, -1, 3, F, 0, 1, nullptr, p->stream));
-  NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, -1, 3, F, 0, 0, nullptr, p->stream));
-  NSF_HIP(p, launch_x_fwd_proj(g, p->ax[0], p->tabs, part, F, reinterpret_cast<double2*>(y2n), nullptr,
-                               p->stream));
+  NSF_HIP(p, pass_yz(p, 2, -1, 3, F, 0, 1, nullptr));
+  NSF_HIP(p, pass_yz(p, 1, -1, 3, F, 0, 0, nullptr));
+  NSF_HIP(p, pass_x_fwd(p, part, F, reinterpret_cast<double2*>(y2n), nullptr));
   return NSF_OK;
 }
 
@@ -397,15 +439,15 @@ int nsf_profile_Ar(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n, int reps, d
   double acc[kPasses] = {0, 0, 0, 0, 0};
   for (int r = 0; r < reps; ++r) {
     NSF_HIP(p, hipEventRecord(ev[0], s));
-    NSF_HIP(p, launch_x_inv_synth(g, p->ax[0], p->tabs, kPartBoth, u, F, nullptr, s));
+    NSF_HIP(p, pass_x_inv(p, kPartBoth, u, F, nullptr));
     NSF_HIP(p, hipEventRecord(ev[1], s));
-    NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, +1, 6, F, 0, 0, nullptr, s));
+    NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, nullptr));
     NSF_HIP(p, hipEventRecord(ev[2], s));
-    NSF_HIP(p, launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), F, nullptr, s));
+    NSF_HIP(p, pass_z_mid(p, F, nullptr));
     NSF_HIP(p, hipEventRecord(ev[3], s));
-    NSF_HIP(p, launch_yz_pass(g, p->ax[1], p->tabs, 1, -1, 6, F, 0, 0, nullptr, s));
+    NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, nullptr));
     NSF_HIP(p, hipEventRecord(ev[4], s));
-    NSF_HIP(p, launch_x_fwd_proj(g, p->ax[0], p->tabs, kPartBoth, F, out, nullptr, s));
+    NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, nullptr));
     NSF_HIP(p, hipEventRecord(ev[5], s));
     NSF_HIP(p, hipEventSynchronize(ev[5]));
     for (int i = 0; i < kPasses; ++i) {

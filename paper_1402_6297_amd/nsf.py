@@ -28,8 +28,11 @@ NSF_E_NOMEM = -6
 NSF_E_HIP = -7
 NSF_E_STATE = -8
 
+NSF_OPT_FFT_PATH = 1
+NSF_OPT_MID_COLS = 2
+
 EXPORTED = [
-    "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query",
+    "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",
     "nsf_set_medium_chiral", "nsf_set_medium_pseudochiral",
     "nsf_apply_Pr", "nsf_apply_Qr", "nsf_apply_PrH", "nsf_apply_QrH",
     "nsf_apply_Ar", "nsf_apply_Br", "nsf_profile_Ar", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
@@ -69,6 +72,7 @@ def lib():
     sig = {
         "nsf_plan_create": (I, [C.POINTER(P), I, I, I, D, DP, D, D, VP]),
         "nsf_plan_destroy": (None, [P]),
+        "nsf_plan_set_option": (I, [P, I, I]),
         "nsf_plan_query": (I, [P, C.POINTER(C.c_longlong), C.POINTER(I), DP, DP]),
         "nsf_set_medium_chiral": (I, [P, VP, VP, I]),
         "nsf_set_medium_pseudochiral": (I, [P, I, I, VP, VP, I]),
@@ -138,6 +142,10 @@ def nsf_plan_create(n1, n2, n3, a, k, alpha=-1.0, beta=2.0, stream=None):
 
 def nsf_plan_destroy(plan):
     lib().nsf_plan_destroy(plan)
+
+
+def nsf_plan_set_option(plan, option, value):
+    return _check(lib().nsf_plan_set_option(plan, int(option), int(value)), plan)
 
 
 def nsf_plan_query(plan):
@@ -281,6 +289,9 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+    def set_option(self, option, value):
+        return nsf_plan_set_option(self.handle, option, value)
 
     def query(self):
         return nsf_plan_query(self.handle)

@@ -48,15 +48,19 @@ BASIS_CASES = [
     ((6, 10, 12), (0.5, 0.5, 0.5)),
     ((48, 16, 20), (0.0, 0.3, 0.0)),
     ((50, 8, 6), (0.2, 0.0, 0.45)),
+    ((128, 16, 32), (0.1, 0.2, 0.3)),
+    ((48, 96, 64), (0.3, 0.1, 0.2)),
 ]
 
 
+@pytest.mark.parametrize("path", [0, 1], ids=["fast", "generic"])
 @pytest.mark.parametrize("grid,k", BASIS_CASES)
-def test_basis_applies_match_oracle(grid, k):
+def test_basis_applies_match_oracle(grid, k, path):
     n = grid[0] * grid[1] * grid[2]
     y = media.random_vector(2 * n, 1)
     x = media.random_vector(3 * n, 2)
     with nsf.Plan(grid, k) as P:
+        P.set_option(nsf.NSF_OPT_FFT_PATH, path)
         out3 = torch.empty(3 * n, dtype=torch.complex128, device="cuda")
         out2 = torch.empty(2 * n, dtype=torch.complex128, device="cuda")
         P.Pr(dev(y), out3)
@@ -91,6 +95,10 @@ def _set(P, eps, gam, pair):
 
 AR_CASES = [
     ((4, 4, 4), (0.1, 0.2, 0.3), "chiral"),
+    ((16, 32, 64), (0.1, 0.2, 0.3), "pseudo_xz"),
+    ((64, 16, 48), (0.3, 0.0, 0.2), "chiral"),
+    ((96, 16, 16), (0.1, 0.4, 0.3), "noise"),
+    ((32, 96, 256), (0.2, 0.1, 0.3), "pseudo_yz"),
     ((3, 4, 5), (0.25, 0.5, 0.1), "pseudo_xz"),
     ((2, 4, 2), (0.5, 0.1, 0.0), "noise"),
     ((16, 16, 16), (0.1, 0.2, 0.3), "chiral"),
@@ -100,21 +108,25 @@ AR_CASES = [
 ]
 
 
+@pytest.mark.parametrize("path", [0, 1], ids=["fast", "generic"])
 @pytest.mark.parametrize("grid,k,kind", AR_CASES)
-def test_Ar_Br_match_oracle(grid, k, kind):
+def test_Ar_Br_match_oracle(grid, k, kind, path):
     n = grid[0] * grid[1] * grid[2]
     eps, gam, tens, pair = _medium(kind, grid)
     u = media.random_vector(4 * n, 5)
     with nsf.Plan(grid, k) as P:
+        P.set_option(nsf.NSF_OPT_FFT_PATH, path)
         _set(P, eps, gam, pair)
         out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
         P.Ar(dev(u), out)
         assert rel(host(out), nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+        # B_r scales by 1/sigma_f; the oracle forms lambda as exp(i theta) - 1, which
+        # loses ~eps/theta relative accuracy at the smallest theta, so 1e-13 here.
         P.Br(dev(u), out)
-        assert rel(host(out), nfgep.apply_Br(u, grid, k)) < 1e-14
+        assert rel(host(out), nfgep.apply_Br(u, grid, k)) < 1e-13
         ud = dev(u)
         P.Br(ud, ud)  # in place is allowed
-        assert rel(host(ud), nfgep.apply_Br(u, grid, k)) < 1e-14
+        assert rel(host(ud), nfgep.apply_Br(u, grid, k)) < 1e-13
 
 
 @pytest.mark.parametrize("grid,k", [((64, 64, 64), (0.25, 0.0, 0.0)), ((128, 128, 128), (0.1, 0.2, 0.3))])
