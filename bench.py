@@ -81,6 +81,10 @@ def main():
     ap.add_argument("--nev", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--matvec-reps", type=int, default=50)
+    ap.add_argument("--fft-path", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_FFT_PATH)")
+    ap.add_argument("--mid-cols", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_MID_COLS)")
+    ap.add_argument("--profile-applies", type=int, default=0,
+                    help="only run this many A_r applies plus a 1 GiB device copy (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -99,6 +103,11 @@ def main():
     eps, gam = make_medium(w)
     print(f"[bench] workload {args.workload}: {w['desc']}", file=sys.stderr, flush=True)
     P = nsf.Plan(grid, k)
+    P.set_option(nsf.NSF_OPT_FFT_PATH, args.fft_path)
+    if args.mid_cols:
+        P.set_option(nsf.NSF_OPT_MID_COLS, args.mid_cols)
+    dev_info = nsf.nsf_device_info(0)
+    print(f"[bench] device {dev_info}", file=sys.stderr, flush=True)
     if w["kind"] == "chiral":
         P.set_chiral(eps, gam)
     else:
@@ -107,6 +116,19 @@ def main():
     # ---- isolated A_r apply: per-kernel HIP-event times and the whole apply
     u = torch.from_numpy(media.random_vector(4 * n, 0)).to("cuda")
     out = torch.empty_like(u)
+    if args.profile_applies:
+        # short run for hardware counters: the applies, then a plain copy of
+        # known size whose FETCH_SIZE / WRITE_SIZE calibrate the counters
+        for _ in range(args.profile_applies):
+            P.Ar(u, out)
+        src = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_applies": args.profile_applies, "copy_bytes": 2 * src.numel() * 16}))
+        return
     for _ in range(10):
         P.Ar(u, out)
     torch.cuda.synchronize()
@@ -158,6 +180,7 @@ def main():
                      "unit": "GB/s", "frac": round(apply_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
                      "kernel": "A_r apply (all kernels of one apply, 336 n B algorithmic)",
                      "kernel_us": [round(x * 1e3, 2) for x in pass_ms]},
+        "device": dev_info,
         "matvec": {"us_per_apply": round(apply_ms * 1e3, 2), "GBps_alg": round(apply_gbps, 2),
                    "bytes_alg": b_alg},
         "eigs": {"status": st, "omega": [round(x, 12) for x in om.tolist()],

@@ -91,10 +91,13 @@ int nsf_plan_create(nsf_plan* out, int n1, int n2, int n3, double a,
 
 /* Tuning options of a plan (nsf_plan_set_option). */
 enum {
-  NSF_OPT_FFT_PATH = 1,  /* 0: register-resident passes where the axis length
-                            allows them (default), 1: generic LDS-staged passes */
+  NSF_OPT_FFT_PATH = 1,  /* 0: two-level register passes where the axis length
+                            allows them, else generic (default),
+                            1: generic LDS-staged passes only,
+                            2: single-wave passes (E'/H' lane halves) for the
+                               x and fused z passes where possible          */
   NSF_OPT_MID_COLS = 2   /* pencils per workgroup of the fused z pass: 1..16,
-                            power of two (default 4)                          */
+                            power of two (default 8)                          */
 };
 
 /*
@@ -233,6 +236,23 @@ int nsf_eig_grad(nsf_plan plan, int nev, const double* omega_host,
  * eigenvector of w[j] (nullable).  1 <= m <= 512.
  */
 int nsf_hermitian_eig(int m, const nsf_c128* H, double* w, nsf_c128* V);
+
+/* Facts about a HIP device (host call; touches the device runtime). */
+typedef struct {
+  char name[64];
+  int compute_units;
+  int clock_khz;
+  int memory_clock_khz;
+  int memory_bus_bits;
+  long long total_memory;
+  long long l2_bytes;
+  int lds_per_block;        /* bytes a workgroup may allocate             */
+  int lds_per_cu;           /* bytes of LDS per compute unit              */
+  int warp_size;
+} nsf_device;
+
+/* Fill *out for HIP device `device`.  NSF_E_HIP if the device is absent. */
+int nsf_device_info(int device, nsf_device* out);
 
 /* Text for a status code (static storage). */
 const char* nsf_status_string(int status);

@@ -176,6 +176,58 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_p(double2* __restrict__ p,
   }
 }
 
+// ----------------------------------------------------- fused CG scalars
+// After the first pass of round k (k > 0) the workgroups have written
+// |r_k|^2 partials: decide convergence on the recurrence residual r_k.
+__global__ __launch_bounds__(kRedThreads) void k_cgf_check(const double* part, int nparts, CgState* st) {
+  if (st->done || st->iter == 0) return;
+  double2 v = make_double2(0, 0);
+  for (int i = threadIdx.x; i < nparts; i += kRedThreads) v.x += part[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) {
+    const double rr = v.x;
+    st->rr = rr;
+    if (!isfinite(rr)) {
+      st->status = NSF_E_BREAKDOWN;
+      st->done = 1;
+    } else if (rr <= st->thresh) {
+      st->status = NSF_OK;
+      st->done = 1;
+    } else if (st->iter >= st->maxit) {
+      st->status = NSF_NOT_CONVERGED;
+      st->done = 1;
+    }
+  }
+}
+
+// After the last pass: alpha = |r|^2 / p^*A p and beta = |r - alpha q|^2 / |r|^2,
+// the new residual norm expanded as |r|^2 - 2 alpha Re r^*q + alpha^2 |q|^2.
+__global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, int nparts, CgState* st) {
+  if (st->done) return;
+  double2 a = make_double2(0, 0), b = make_double2(0, 0);
+  for (int i = threadIdx.x; i < nparts; i += kRedThreads) {
+    a.x += part[3 * i];
+    a.y += part[3 * i + 1];
+    b.x += part[3 * i + 2];
+  }
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) {
+    const double pq = a.x, qq = a.y, rq = b.x, rr = st->rr;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      st->status = NSF_E_BREAKDOWN;
+      st->done = 1;
+      return;
+    }
+    const double al = rr / pq;
+    double rn = rr - 2.0 * al * rq + al * al * qq;
+    if (rn < 0.0) rn = 0.0;
+    st->alpha = al;
+    st->beta = rn / rr;
+    st->iter += 1;
+  }
+}
+
 // ------------------------------------------------------- multi-vector ops
 constexpr int kDotChunk = 4;  // basis vectors per workgroup of the multi-dot
 
@@ -352,6 +404,16 @@ hipError_t launch_cg_beta(const double2* partial, int nparts, CgState* st, hipSt
 
 hipError_t launch_cg_p(double2* p, const double2* r, long long len, CgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_p, dim3(red_grid(len)), dim3(kRedThreads), 0, s, p, r, len, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgf_check, dim3(1), dim3(kRedThreads), 0, s, part_in, nparts, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgf_step, dim3(1), dim3(kRedThreads), 0, s, part_out, nparts, st);
   return hipGetLastError();
 }
 

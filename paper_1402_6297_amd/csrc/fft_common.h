@@ -168,6 +168,43 @@ struct Basis {
   double2 pi1[3], pi2[3];
 };
 
+// Sum of up to four doubles over a workgroup of at most 1024 threads; the
+// result is valid in thread 0.  Fixed order: wave butterflies, then waves in
+// index order.
+template <int K>
+__device__ __forceinline__ void block_sum_k(double (&v)[K]) {
+  __shared__ double red[16][K];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double a = 0;
+      for (int w = 0; w < nw; ++w) a += red[w][k];
+      v[k] = a;
+    }
+  }
+}
+
+// Loads and stores at a workgroup-uniform base plus a 32-bit lane offset (in
+// elements), so the compiler can use SGPR-base addressing instead of holding
+// a 64-bit address per load in VGPRs.  Offsets times 16 must stay below 2^32.
+__device__ __forceinline__ double2 ld_off(const double2* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (off << 4));
+}
+__device__ __forceinline__ void st_off(double2* __restrict__ base, unsigned off, double2 v) {
+  *reinterpret_cast<double2*>(reinterpret_cast<char*>(base) + (off << 4)) = v;
+}
+
 __device__ __forceinline__ void basis_at(const double2* __restrict__ lam, const Geom& g, int i1, int i2,
                                 int i3, Basis& B) {
   const double2 l1 = lam[i1], l2 = lam[g.n1 + i2], l3 = lam[g.n1 + g.n2 + i3];

@@ -192,10 +192,10 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
 
 // ------------------------------------------------------------- x passes
 // R rows per workgroup; LDS tile[(c * R + r) * (N + 1) + e].
-template <int N1, int N2, int PART>
+template <int N1, int N2, int PART, bool CG = false>
 __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const double2* __restrict__ y,
                                                       double2* __restrict__ fld, int R,
-                                                      const int* skip) {
+                                                      const int* skip, CgFuse cg = CgFuse{}) {
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
   constexpr int NP = N + 1;
@@ -208,6 +208,14 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   const long long rows = (long long)g.n2 * g.n3;
   const long long row0 = (long long)blockIdx.x * R;
   const long long n = g.n;
+  double rr_acc[1] = {0.0};
+  int cg_iter = 0;
+  double cg_al = 0, cg_be = 0;
+  if (CG) {
+    cg_iter = cg.st->iter;
+    cg_al = cg.st->alpha;
+    cg_be = cg.st->beta;
+  }
   // synthesis of the coefficient fields, one frequency per thread and step
   for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
     const int r = e / N, i1 = e - r * N;
@@ -217,8 +225,31 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
     const long long f = row * N + i1;
     Basis B;
     basis_at(t.lam, g, i1, i2, i3, B);
+    double2 yv[4];
+    if (CG) {
+      // CG recurrences of the previous iteration, then this iteration's p
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const long long o = b * n + f;
+        const double2 po = cg.p[o];
+        if (cg_iter > 0) {
+          const double2 qo = cg.q[o];
+          double2 rv = cg.r[o], xv = cg.x[o];
+          rv = make_double2(rv.x - cg_al * qo.x, rv.y - cg_al * qo.y);
+          xv = make_double2(xv.x + cg_al * po.x, xv.y + cg_al * po.y);
+          const double2 pn = make_double2(rv.x + cg_be * po.x, rv.y + cg_be * po.y);
+          cg.r[o] = rv;
+          cg.x[o] = xv;
+          cg.p[o] = pn;
+          rr_acc[0] += cabs2(rv);
+          yv[b] = pn;
+        } else {
+          yv[b] = po;
+        }
+      }
+    }
     if (PART == kPartBoth || PART == kPartP) {
-      const double2 ya = y[f], yb = y[n + f];
+      const double2 ya = CG ? yv[0] : y[f], yb = CG ? yv[1] : y[n + f];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
         tile[(cc * R + r) * NP + i1] = csub(cmulc(B.pi1[cc], yb), cmulc(B.pi2[cc], ya));
@@ -226,11 +257,15 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
     if (PART == kPartBoth || PART == kPartQ) {
       const long long o = (PART == kPartBoth) ? 2 * n : 0;
       const int cb = (PART == kPartBoth) ? 3 : 0;
-      const double2 yc = y[o + f], yd = y[o + n + f];
+      const double2 yc = CG ? yv[2] : y[o + f], yd = CG ? yv[3] : y[o + n + f];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
         tile[((cb + cc) * R + r) * NP + i1] = cadd(cmul(B.pi1[cc], yc), cmul(B.pi2[cc], yd));
     }
+  }
+  if (CG) {
+    block_sum_k<1>(rr_acc);
+    if (threadIdx.x == 0) cg.part_in[blockIdx.x] = rr_acc[0];
   }
   __syncthreads();
   const int n2 = threadIdx.x % N2;
@@ -266,10 +301,10 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   }
 }
 
-template <int N1, int N2, int PART>
+template <int N1, int N2, int PART, bool CG = false>
 __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
                                                      double2* __restrict__ out, int R,
-                                                     const int* skip) {
+                                                     const int* skip, CgFuse cg = CgFuse{}) {
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
   constexpr int NP = N + 1;
@@ -324,6 +359,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
     }
   }
   __syncthreads();
+  double acc[3] = {0.0, 0.0, 0.0};  // Re p^*q, |q|^2, Re r^*q (fused CG)
   // projection, one frequency per thread and step
   for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
     const int rr = e / N, i1 = e - rr * N;
@@ -333,8 +369,8 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
     const long long f = row * N + i1;
     Basis B;
     basis_at(t.lam, g, i1, i2, i3, B);
+    double2 oa = make_double2(0, 0), ob = make_double2(0, 0);
     if (PART == kPartBoth || PART == kPartP) {
-      double2 oa = make_double2(0, 0), ob = make_double2(0, 0);
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
         const double2 o = tile[(cc * R + rr) * NP + i1];
@@ -356,6 +392,25 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       }
       out[o0 + f] = oc;
       out[o0 + n + f] = od;
+      if (CG) {
+        const double2 qv[4] = {oa, ob, oc, od};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const long long ofs = b * n + f;
+          const double2 pv = cg.p[ofs], rv = cg.r[ofs];
+          acc[0] += pv.x * qv[b].x + pv.y * qv[b].y;
+          acc[1] += cabs2(qv[b]);
+          acc[2] += rv.x * qv[b].x + rv.y * qv[b].y;
+        }
+      }
+    }
+  }
+  if (CG) {
+    block_sum_k<3>(acc);
+    if (threadIdx.x == 0) {
+      cg.part_out[3 * blockIdx.x + 0] = acc[0];
+      cg.part_out[3 * blockIdx.x + 1] = acc[1];
+      cg.part_out[3 * blockIdx.x + 2] = acc[2];
     }
   }
 }
@@ -389,6 +444,20 @@ bool fast_cfg(int N, FastCfg& c) {
     case 48: MACRO(16, 3); break;  \
     default: return hipErrorInvalidValue; \
   }
+
+// Largest LDS allocation one workgroup may make on the current device.
+size_t lds_limit() {
+  static size_t cached = 0;
+  if (!cached) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      cached = (size_t)v;
+    else
+      cached = 65536;
+  }
+  return cached;
+}
 
 int pick_cols(int n1, int want) {
   int P = 1;
@@ -431,12 +500,19 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
   int P = pick_cols(g.n1, P_want);
-  while (P > 1 && (6 * P * cfg.N2 > 384 || (size_t)(N + 6 * N * P) * 16 > 64 * 1024)) P /= 2;
+  while (P > 1 && (6 * P * cfg.N2 > 384 || (size_t)(N + 6 * N * P) * 16 > lds_limit())) P /= 2;
   if (6 * P * cfg.N2 > 384) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((g.n1 / P) * g.n2));
   const dim3 block(6 * P * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * N * P);
-#define L_MID(A, B) hipLaunchKernelGGL((k_fz_mid<A, B>), grid, block, lds, s, g, t, med, fld, P, skip);
+  // Workgroups above 64 KiB of LDS opt in once per kernel.
+#define L_MID(A, B)                                                                                 \
+  if (lds > 65536) {                                                                                \
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_mid<A, B>),       \
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    if (e != hipSuccess) return e;                                                                  \
+  }                                                                                                 \
+  hipLaunchKernelGGL((k_fz_mid<A, B>), grid, block, lds, s, g, t, med, fld, P, skip);
   NSF_FAST_SWITCH(N, L_MID)
 #undef L_MID
   return hipGetLastError();
@@ -489,6 +565,58 @@ hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, cons
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartQ>), grid, block, lds, s, g, t, fld, out, R, skip);
   NSF_FAST_SWITCH(N, L_XF)
 #undef L_XF
+  return hipGetLastError();
+}
+
+// Rows per workgroup of the six-field x passes (0: no two-level pass).
+int fast_x_rows(const Geom& g) {
+  const int N = g.n1;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg)) return 0;
+  int R = 4;
+  while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
+  return 6 * R * cfg.N2 > 384 ? 0 : R;
+}
+
+hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg, double2* fld,
+                                const int* skip, int* nparts, hipStream_t s) {
+  const int N = g.n1;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
+  int R = 4;
+  while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
+  if (6 * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const long long rows = (long long)g.n2 * g.n3;
+  const dim3 grid((unsigned)((rows + R - 1) / R));
+  *nparts = (int)grid.x;
+  const dim3 block(6 * R * cfg.N2);
+  const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
+#define L_CGI(A, B)                                                                                  \
+  hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true>), grid, block, lds, s, g, t,             \
+                     (const double2*)nullptr, fld, R, skip, cg);
+  NSF_FAST_SWITCH(N, L_CGI)
+#undef L_CGI
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
+                               const int* skip, int* nparts, hipStream_t s) {
+  const int N = g.n1;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
+  int R = 4;
+  while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
+  if (6 * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const long long rows = (long long)g.n2 * g.n3;
+  const dim3 grid((unsigned)((rows + R - 1) / R));
+  *nparts = (int)grid.x;
+  const dim3 block(6 * R * cfg.N2);
+  const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
+#define L_CGL(A, B)                                                                                  \
+  hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true>), grid, block, lds, s, g, t, fld, cg.q,   \
+                     R, skip, cg);
+  NSF_FAST_SWITCH(N, L_CGL)
+#undef L_CGL
   return hipGetLastError();
 }
 

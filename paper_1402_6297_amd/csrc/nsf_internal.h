@@ -112,6 +112,17 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
 hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld,
                                   double2* out, const int* skip, hipStream_t s);
 
+// Single-wave passes holding E' / H' components per lane (axis lengths 16,
+// 32, 64, 128); same semantics again.
+bool wave_axis(int N);
+bool wave_mid_ok(const Geom& g);
+hipError_t launch_wave_x_inv_synth(const Geom& g, const Tables& t, int part, const double2* y,
+                                   double2* fld, const int* skip, hipStream_t s);
+hipError_t launch_wave_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
+                             const int* skip, hipStream_t s);
+hipError_t launch_wave_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld,
+                                  double2* out, const int* skip, hipStream_t s);
+
 // out = B_r u (Thm 4.2): per frequency 1/sigma_f times i / -i block swaps.
 hipError_t launch_apply_Br(const Geom& g, const Tables& t, const double2* u, double2* out,
                            const int* skip, hipStream_t s);
@@ -131,6 +142,35 @@ struct CgState {
   int status;       // NSF_OK / NSF_NOT_CONVERGED / NSF_E_BREAKDOWN
   int pad[3];
 };
+
+// Vectors and device scalars of a CG solve whose recurrences are fused into
+// the first and last FFT pass of each A_r apply (see launch_fast_cg_*).
+struct CgFuse {
+  double2* x;
+  double2* r;
+  double2* p;
+  double2* q;
+  const CgState* st;
+  double* part_in;   // per-workgroup |r|^2 of the first pass
+  double* part_out;  // per-workgroup (Re p^*q, |q|^2, Re r^*q) of the last pass
+};
+
+// First pass of a fused CG iteration: for iter > 0 it forms
+// r = r - alpha q, x = x + alpha p, p = r + beta p (with alpha, beta of the
+// previous iteration), writes them and the per-workgroup |r|^2, then
+// synthesises from p exactly like launch_fast_x_inv_synth.  Returns the
+// number of workgroups through *nparts.
+int fast_x_rows(const Geom& g);
+hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg, double2* fld,
+                                const int* skip, int* nparts, hipStream_t s);
+// Last pass: q = projection of the forward x transform (written to cg.q) and
+// the per-workgroup partial sums of p^*q, |q|^2, r^*q.
+hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
+                               const int* skip, int* nparts, hipStream_t s);
+// Scalar steps of the fused CG: check |r|^2 after the first pass, then alpha,
+// beta from the last pass (|r - alpha q|^2 by expansion).
+hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipStream_t s);
+hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s);
 
 // partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
 hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,
@@ -216,8 +256,8 @@ struct nsf_plan_s {
   size_t basis_vectors = 0;    // capacity of V (and of AV)
 
   // options (nsf_plan_set_option)
-  int opt_generic_fft = 0;  // 1: always use the generic LDS-staged passes
-  int opt_mid_cols = 4;     // pencils per workgroup of the fused z pass
+  int opt_fft_path = 0;     // 0 auto, 1 generic LDS-staged, 2 two-level without single-wave
+  int opt_mid_cols = 8;     // pencils per workgroup of the fused z pass
 
   std::string last_error;
 };

@@ -89,7 +89,9 @@ MediumView medium_view(nsf_plan p) {
 
 hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, const int* skip) {
   const Geom& g = p->geom;
-  if (!p->opt_generic_fft && fast_axis(g.n1))
+  if (p->opt_fft_path == 2 && wave_axis(g.n1) && g.n <= (1LL << 32) / 96)
+    return launch_wave_x_inv_synth(g, p->tabs, part, y, fld, skip, p->stream);
+  if (p->opt_fft_path != 1 && fast_axis(g.n1))
     return launch_fast_x_inv_synth(g, p->tabs, part, y, fld, skip, p->stream);
   return launch_x_inv_synth(g, p->ax[0], p->tabs, part, y, fld, skip, p->stream);
 }
@@ -97,21 +99,25 @@ hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, cons
 hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post_twist, int pre_twist,
                    const int* skip) {
   const Geom& g = p->geom;
-  if (!p->opt_generic_fft && fast_axis(axis == 1 ? g.n2 : g.n3))
+  if (p->opt_fft_path != 1 && fast_axis(axis == 1 ? g.n2 : g.n3))
     return launch_fast_yz(g, p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
   return launch_yz_pass(g, p->ax[axis], p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
 }
 
 hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip) {
   const Geom& g = p->geom;
-  if (!p->opt_generic_fft && fast_axis(g.n3))
+  if (p->opt_fft_path == 2 && wave_mid_ok(g))
+    return launch_wave_z_mid(g, p->tabs, medium_view(p), fld, skip, p->stream);
+  if (p->opt_fft_path != 1 && fast_axis(g.n3))
     return launch_fast_z_mid(g, p->tabs, medium_view(p), fld, p->opt_mid_cols, skip, p->stream);
   return launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), fld, skip, p->stream);
 }
 
 hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip) {
   const Geom& g = p->geom;
-  if (!p->opt_generic_fft && fast_axis(g.n1))
+  if (p->opt_fft_path == 2 && wave_axis(g.n1) && g.n <= (1LL << 32) / 96)
+    return launch_wave_x_fwd_proj(g, p->tabs, part, fld, out, skip, p->stream);
+  if (p->opt_fft_path != 1 && fast_axis(g.n1))
     return launch_fast_x_fwd_proj(g, p->tabs, part, fld, out, skip, p->stream);
   return launch_x_fwd_proj(g, p->ax[0], p->tabs, part, fld, out, skip, p->stream);
 }
@@ -150,6 +156,24 @@ const char* nsf_status_string(int status) {
     case NSF_E_STATE: return "plan is missing required state";
     default: return "unknown status";
   }
+}
+
+int nsf_device_info(int device, nsf_device* out) {
+  if (!out) return set_error(nullptr, NSF_E_ARG, "out is NULL");
+  hipDeviceProp_t prop;
+  NSF_HIP(nullptr, hipGetDeviceProperties(&prop, device));
+  std::memset(out, 0, sizeof(*out));
+  std::snprintf(out->name, sizeof(out->name), "%s", prop.gcnArchName);
+  out->compute_units = prop.multiProcessorCount;
+  out->clock_khz = prop.clockRate;
+  out->memory_clock_khz = prop.memoryClockRate;
+  out->memory_bus_bits = prop.memoryBusWidth;
+  out->total_memory = (long long)prop.totalGlobalMem;
+  out->l2_bytes = prop.l2CacheSize;
+  out->lds_per_block = (int)prop.sharedMemPerBlock;
+  out->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+  out->warp_size = prop.warpSize;
+  return NSF_OK;
 }
 
 const char* nsf_last_error(nsf_plan plan) {
@@ -275,8 +299,8 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
   if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
   switch (option) {
     case NSF_OPT_FFT_PATH:
-      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_FFT_PATH takes 0 or 1");
-      p->opt_generic_fft = value;
+      if (value < 0 || value > 2) return set_error(p, NSF_E_ARG, "NSF_OPT_FFT_PATH takes 0, 1 or 2");
+      p->opt_fft_path = value;
       return NSF_OK;
     case NSF_OPT_MID_COLS:
       if (value < 1 || value > 16 || (value & (value - 1))) return set_error(p, NSF_E_ARG, "NSF_OPT_MID_COLS takes 1, 2, 4, 8 or 16");

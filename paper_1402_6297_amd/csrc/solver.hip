@@ -69,11 +69,29 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
   const int nparts = reduce_parts_for(len);
   const int* skip = &st->done;
   NSF_HIP(p, launch_cg_init(b, x, r, pp, len, p->d_partial, st, rtol, maxit, s));
+  // Fused iterations when the x axis has a two-level pass: the CG updates
+  // ride in the first and last FFT pass of every A_r apply.
+  const Geom& g = p->geom;
+  const int xr = fast_x_rows(g);
+  const bool fused = p->opt_fft_path != 1 && xr > 0 && ((long long)g.n2 * g.n3 + xr - 1) / xr <= 65536;
+  CgFuse cgf{x, r, pp, q, st, reinterpret_cast<double*>(p->d_partial),
+             reinterpret_cast<double*>(p->d_partial) + 65536};
   int chunk = 4;
   double rr_prev = -1.0;
   int it_prev = 0;
   for (;;) {
     for (int c = 0; c < chunk; ++c) {
+      if (fused) {
+        int np1 = 0, np5 = 0;
+        NSF_HIP(p, launch_fast_cg_first(g, p->tabs, cgf, p->d_fields, skip, &np1, s));
+        NSF_HIP(p, launch_cgf_check(cgf.part_in, np1, st, s));
+        NSF_HIP(p, pass_yz(p, 1, +1, 6, p->d_fields, 0, 0, skip));
+        NSF_HIP(p, pass_z_mid(p, p->d_fields, skip));
+        NSF_HIP(p, pass_yz(p, 1, -1, 6, p->d_fields, 0, 0, skip));
+        NSF_HIP(p, launch_fast_cg_last(g, p->tabs, cgf, p->d_fields, skip, &np5, s));
+        NSF_HIP(p, launch_cgf_step(cgf.part_out, np5, st, s));
+        continue;
+      }
       rc = apply_Ar_dev(p, pp, q, skip);
       if (rc) return rc;
       NSF_HIP(p, launch_dot_partials(pp, q, len, p->d_partial, skip, s));

@@ -36,7 +36,7 @@ EXPORTED = [
     "nsf_set_medium_chiral", "nsf_set_medium_pseudochiral",
     "nsf_apply_Pr", "nsf_apply_Qr", "nsf_apply_PrH", "nsf_apply_QrH",
     "nsf_apply_Ar", "nsf_apply_Br", "nsf_profile_Ar", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
-    "nsf_hermitian_eig", "nsf_status_string", "nsf_last_error",
+    "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
 ]
 
 
@@ -48,6 +48,18 @@ class nsf_stats(C.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class nsf_device(C.Structure):
+    _fields_ = [("name", C.c_char * 64), ("compute_units", C.c_int), ("clock_khz", C.c_int),
+                ("memory_clock_khz", C.c_int), ("memory_bus_bits", C.c_int),
+                ("total_memory", C.c_longlong), ("l2_bytes", C.c_longlong),
+                ("lds_per_block", C.c_int), ("lds_per_cu", C.c_int), ("warp_size", C.c_int)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["name"] = d["name"].decode()
+        return d
 
 
 class NsfError(RuntimeError):
@@ -87,6 +99,7 @@ def lib():
         "nsf_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, VP, DP, C.POINTER(nsf_stats)]),
         "nsf_eig_grad": (I, [P, I, DP, VP, DP, VP, VP]),
         "nsf_hermitian_eig": (I, [I, VP, DP, VP]),
+        "nsf_device_info": (I, [I, C.POINTER(nsf_device)]),
         "nsf_status_string": (C.c_char_p, [I]),
         "nsf_last_error": (C.c_char_p, [P]),
     }
@@ -251,6 +264,12 @@ def nsf_hermitian_eig(H):
     _check(lib().nsf_hermitian_eig(m, C.c_void_p(H.ctypes.data), w.ctypes.data_as(C.POINTER(C.c_double)),
                                    C.c_void_p(V.ctypes.data)))
     return w, V
+
+
+def nsf_device_info(device=0):
+    d = nsf_device()
+    _check(lib().nsf_device_info(int(device), C.byref(d)))
+    return d.as_dict()
 
 
 def nsf_status_string(status):

@@ -53,7 +53,7 @@ BASIS_CASES = [
 ]
 
 
-@pytest.mark.parametrize("path", [0, 1], ids=["fast", "generic"])
+@pytest.mark.parametrize("path", [0, 1, 2], ids=["auto", "generic", "twolevel"])
 @pytest.mark.parametrize("grid,k", BASIS_CASES)
 def test_basis_applies_match_oracle(grid, k, path):
     n = grid[0] * grid[1] * grid[2]
@@ -108,7 +108,7 @@ AR_CASES = [
 ]
 
 
-@pytest.mark.parametrize("path", [0, 1], ids=["fast", "generic"])
+@pytest.mark.parametrize("path", [0, 1, 2], ids=["auto", "generic", "twolevel"])
 @pytest.mark.parametrize("grid,k,kind", AR_CASES)
 def test_Ar_Br_match_oracle(grid, k, kind, path):
     n = grid[0] * grid[1] * grid[2]
