@@ -72,6 +72,70 @@ def cpu_baseline(w, eps, gam, budget_s=20.0):
                 host_cpu=platform.processor() or platform.machine())
 
 
+def kernel_source_hash():
+    """Hash of the HIP sources: stored traffic figures apply only to these kernels."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_1402_6297_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _kernel_key(name):
+    import re
+
+    m = re.search(r"::(k_\w+(<[^>]*>)?)", name)
+    return m.group(1) if m else name.split("(")[0][:60]
+
+
+def summarize_trace(d):
+    """Markdown table of a rocprofv3 --kernel-trace --stats CSV directory."""
+    import csv
+    import glob
+
+    path = glob.glob(os.path.join(d, "*kernel_stats.csv"))[0]
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{_kernel_key(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def summarize_pmc(fetch_dir, write_dir, applies, workload):
+    """Per-kernel HBM bytes from FETCH_SIZE / WRITE_SIZE runs, calibrated on the
+    1 GiB device copy of the same run (known: 1 GiB read, 1 GiB written)."""
+    import collections
+    import csv
+    import glob
+
+    def load(d, ctr):
+        rows = list(csv.DictReader(open(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])))
+        acc = collections.defaultdict(list)
+        for r in rows:
+            if r["Counter_Name"] == ctr:
+                acc[_kernel_key(r["Kernel_Name"])].append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy = "__amd_rocclr_copyBuffer"
+    f_scale = (1 << 30) / (sum(fe[copy]) / len(fe[copy]))
+    w_scale = (1 << 30) / (sum(wr[copy]) / len(wr[copy]))
+    kernels = {}
+    for k in fe:
+        if not k.startswith("k_"):
+            continue
+        fb = sum(fe[k]) / len(fe[k]) * f_scale
+        wb = sum(wr.get(k, [0.0])) / max(len(wr.get(k, [1])), 1) * w_scale
+        kernels[k] = {"fetch_bytes": fb, "write_bytes": wb, "launches": len(fe[k])}
+    per_apply = sum((v["fetch_bytes"] + v["write_bytes"]) * v["launches"] for v in kernels.values()) / applies
+    return {"workload": workload, "source_hash": kernel_source_hash(), "fetch_scale": f_scale,
+            "write_scale": w_scale, "kernels": kernels, "bytes_per_apply": per_apply}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,7 +149,20 @@ def main():
     ap.add_argument("--mid-cols", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_MID_COLS)")
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="only run this many A_r applies plus a 1 GiB device copy (for rocprofv3)")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="print a rocprofv3 kernel-stats table and exit")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ar_apply_traffic_<workload>.json from two --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_pmc:
+        res = summarize_pmc(*args.summarize_pmc, applies=args.profile_applies or 3, workload=args.workload)
+        path = os.path.join(ROOT, "profiles", f"ar_apply_traffic_{args.workload}.json")
+        with open(path, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "independent k-points shard across GPUs without communication, see DESIGN.md",
@@ -135,6 +212,12 @@ def main():
     pass_ms, apply_ms = P.profile_Ar(u, out, reps=args.matvec_reps)
     b_alg = BYTES_PER_APPLY_PER_N * n
     apply_gbps = b_alg / (apply_ms * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"ar_apply_traffic_{args.workload}.json")
+    if os.path.exists(tpath):
+        t = json.load(open(tpath))
+        if t.get("source_hash") == kernel_source_hash() and args.fft_path == 0:
+            traffic = round(t["bytes_per_apply"])
     print(f"[bench] A_r apply {apply_ms * 1e3:.1f} us, {apply_gbps:.0f} GB/s algorithmic; "
           f"kernels (us): {[round(x * 1e3, 1) for x in pass_ms]}", file=sys.stderr, flush=True)
 
@@ -177,7 +260,7 @@ def main():
                                f"CG rtol 1e-10, residual <= 1e-8, complex128",
                    "grid": list(grid), "k": list(k), "nev": nev, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": round(apply_gbps, 2), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(apply_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(apply_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "A_r apply (all kernels of one apply, 336 n B algorithmic)",
                      "kernel_us": [round(x * 1e3, 2) for x in pass_ms]},
         "device": dev_info,

@@ -50,6 +50,7 @@ typedef struct {
   int lanczos_steps;         /* basis expansions                                */
   int restarts;              /* thick restarts                                  */
   int converged;             /* wanted pairs with residual <= res_tol           */
+  int ortho_passes;          /* Gram-Schmidt passes over the basis              */
   double cg_iters_avg;       /* cg_iters_total / cg_solves                      */
   double ms_total;           /* wall time of the call (host clock)              */
   double bytes_alg;          /* algorithmic HBM bytes of the A_r applies        */

@@ -109,7 +109,7 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
     if (rr_prev > 0 && h.rr > 0 && h.rr < rr_prev && h.iter > it_prev) {
       const double rate = std::log(rr_prev / h.rr) / (h.iter - it_prev);
       const double need = std::log(h.rr / h.thresh) / rate;
-      next = (int)std::ceil(need);
+      next = (int)std::ceil(need) + (fused ? 1 : 0);
     }
     rr_prev = h.rr;
     it_prev = h.iter;
@@ -272,12 +272,10 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
 
   // Make V[j] the A_r-normalised copy of `w` (AV[j] from z) and fill row/col j
   // of H; leaves B_r V[j] in bv.
-  auto admit = [&](int j) -> int {
-    double2 nrm;
-    int r2 = dot_host(p, w, z, len, &nrm);
-    if (r2) return r2;
-    if (!(nrm.x > 0.0) || !std::isfinite(nrm.x)) return set_error(p, NSF_E_BREAKDOWN, "A_r-norm of a new basis vector is not positive");
-    const double sc = 1.0 / std::sqrt(nrm.x);
+  auto admit = [&](int j, double nrm2) -> int {
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+      return set_error(p, NSF_E_BREAKDOWN, "A_r-norm of a new basis vector is not positive");
+    const double sc = 1.0 / std::sqrt(nrm2);
     NSF_HIP(p, launch_scale_copy(w, V + (size_t)j * len, sc, 0.0, len, s));
     NSF_HIP(p, launch_scale_copy(z, AV + (size_t)j * len, sc, 0.0, len, s));
     NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, V + (size_t)j * len, bv, nullptr, s));
@@ -291,13 +289,26 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
     Hat(j, j).y = 0.0;
     return NSF_OK;
   };
-  // Orthogonalise (w, z) against V[0..nb) in the A_r inner product, twice.
-  auto orthogonalise = [&](int nb) -> int {
+  // Orthogonalise (w, z) against V[0..nb) in the A_r inner product by
+  // classical Gram-Schmidt; a second pass runs only when the first removed
+  // more than half of the A-norm squared (the Daniel-Gragg-Kaufman-Stewart
+  // test), which is when cancellation can leave w short of orthogonal.
+  auto orthogonalise = [&](int nb, double* norm2, double* norm2_in) -> int {
+    double2 before, after;
+    int r2 = dot_host(p, w, z, len, &before);
+    if (r2) return r2;
+    *norm2_in = before.x;
     for (int pass = 0; pass < 2; ++pass) {
       NSF_HIP(p, launch_multi_dot(AV, len, nb, w, len, p->d_partial, dcoef, s));
       NSF_HIP(p, launch_multi_axpy(V, len, nb, dcoef, w, len, s));
       NSF_HIP(p, launch_multi_axpy(AV, len, nb, dcoef, z, len, s));
+      r2 = dot_host(p, w, z, len, &after);
+      if (r2) return r2;
+      st.ortho_passes += 1;
+      if (after.x > 0.5 * before.x) break;
+      before = after;
     }
+    *norm2 = after.x;
     return NSF_OK;
   };
   auto cleanup = [&](int code) { return code; };
@@ -307,8 +318,13 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
   rc = apply_Ar_dev(p, w, z, nullptr);
   if (rc) return cleanup(rc);
   st.matvecs += 1;
-  rc = admit(0);
-  if (rc) return cleanup(rc);
+  {
+    double2 n0;
+    rc = dot_host(p, w, z, len, &n0);
+    if (rc) return cleanup(rc);
+    rc = admit(0, n0.x);
+    if (rc) return cleanup(rc);
+  }
   int nb = 1;
   bool converged = false;
   for (;;) {
@@ -322,23 +338,19 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
     rc = apply_Ar_dev(p, w, z, nullptr);
     if (rc) return cleanup(rc);
     st.matvecs += 1;
-    rc = orthogonalise(nb);
+    double nw = 0.0, nw_in = 0.0;
+    rc = orthogonalise(nb, &nw, &nw_in);
     if (rc) return cleanup(rc);
-    {  // invariant subspace: continue from a fresh random direction
-      double2 nw, nz;
-      rc = dot_host(p, w, z, len, &nw);
+    if (!(nw > 1e-20 * nw_in)) {
+      // invariant subspace: continue from a fresh random direction
+      NSF_HIP(p, launch_randn(w, len, seed + 7919ULL * (st.lanczos_steps + 1), s));
+      rc = apply_Ar_dev(p, w, z, nullptr);
       if (rc) return cleanup(rc);
-      if (!(nw.x > 1e-24 * std::fabs(Hat(nb - 1, nb - 1).x) + 1e-300)) {
-        NSF_HIP(p, launch_randn(w, len, seed + 7919ULL * (st.lanczos_steps + 1), s));
-        rc = apply_Ar_dev(p, w, z, nullptr);
-        if (rc) return cleanup(rc);
-        st.matvecs += 1;
-        rc = orthogonalise(nb);
-        if (rc) return cleanup(rc);
-        (void)nz;
-      }
+      st.matvecs += 1;
+      rc = orthogonalise(nb, &nw, &nw_in);
+      if (rc) return cleanup(rc);
     }
-    rc = admit(nb);
+    rc = admit(nb, nw);
     if (rc) return cleanup(rc);
     nb += 1;
     st.lanczos_steps += 1;

@@ -43,7 +43,8 @@ EXPORTED = [
 class nsf_stats(C.Structure):
     _fields_ = [("matvecs", C.c_longlong), ("cg_iters_total", C.c_longlong),
                 ("cg_solves", C.c_int), ("lanczos_steps", C.c_int), ("restarts", C.c_int),
-                ("converged", C.c_int), ("cg_iters_avg", C.c_double), ("ms_total", C.c_double),
+                ("converged", C.c_int), ("ortho_passes", C.c_int), ("cg_iters_avg", C.c_double),
+                ("ms_total", C.c_double),
                 ("bytes_alg", C.c_double)]
 
     def as_dict(self):
