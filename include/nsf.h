@@ -231,6 +231,35 @@ int nsf_eig_grad(nsf_plan plan, int nev, const double* omega_host,
                  double* d_eps_dev, double* d_gamma_dev);
 
 /*
+ * Batches: many independent instances (Bloch vectors, grids, media) solved in
+ * one schedule.  Instances with the same grid share every launch of the CG
+ * iterations and A_r applies (the instance is a launch dimension, each with
+ * its own convergence flag), and the host synchronises once per Lanczos
+ * phase for the whole batch.  Results equal per-instance nsf_eigs calls up to
+ * rounding and the start vectors (instance i uses seed + 1000003 i).
+ *
+ * nsf_batch_create: count instances; grids is count x 3 (n1, n2, n3), ks is
+ *   count x 3 Bloch vectors; a, alpha, beta as nsf_plan_create; all instances
+ *   enqueue on hip_stream.  Errors as nsf_plan_create (message names the
+ *   instance).
+ * nsf_batch_plan: borrow instance i's plan (owned by the batch) to set its
+ *   medium or options, or to call single-instance functions on it.
+ * nsf_batch_eigs: as nsf_eigs for every instance; omega_host and resid_host
+ *   are count x nev (row i for instance i), stats count entries (nullable).
+ *   Instances run in waves sized to free device memory; *wave_size (nullable)
+ *   receives the wave length.  Returns NSF_OK when every instance converged,
+ *   NSF_NOT_CONVERGED otherwise, or an error.  Synchronises.
+ */
+typedef struct nsf_batch_s* nsf_batch;
+int nsf_batch_create(nsf_batch* out, int count, const int* grids, const double* ks, double a,
+                     double alpha, double beta, void* hip_stream);
+int nsf_batch_plan(nsf_batch batch, int i, nsf_plan* plan);
+int nsf_batch_eigs(nsf_batch batch, int nev, double res_tol, double cg_rtol, int max_basis,
+                   int max_restarts, unsigned long long seed, double* omega_host,
+                   double* resid_host, nsf_stats* stats, int* wave_size);
+void nsf_batch_destroy(nsf_batch batch);
+
+/*
  * Dense Hermitian eigensolver on the host (cyclic complex Jacobi), the small
  * projected problem of the Lanczos method.  H: host m x m, row-major, only read.
  * w: host m ascending eigenvalues.  V: host m x m, row-major, column j is the

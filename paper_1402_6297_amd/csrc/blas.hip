@@ -179,7 +179,12 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_p(double2* __restrict__ p,
 // ----------------------------------------------------- fused CG scalars
 // After the first pass of round k (k > 0) the workgroups have written
 // |r_k|^2 partials: decide convergence on the recurrence residual r_k.
-__global__ __launch_bounds__(kRedThreads) void k_cgf_check(const double* part, int nparts, CgState* st) {
+__global__ __launch_bounds__(kRedThreads) void k_cgf_check(const double* part, int nparts, CgState* st,
+                                                           const InstDesc* insts) {
+  if (insts) {
+    part = insts[blockIdx.x].cg.part_in;
+    st = insts[blockIdx.x].cg.st;
+  }
   if (st->done || st->iter == 0) return;
   double2 v = make_double2(0, 0);
   for (int i = threadIdx.x; i < nparts; i += kRedThreads) v.x += part[i];
@@ -202,7 +207,12 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_check(const double* part, i
 
 // After the last pass: alpha = |r|^2 / p^*A p and beta = |r - alpha q|^2 / |r|^2,
 // the new residual norm expanded as |r|^2 - 2 alpha Re r^*q + alpha^2 |q|^2.
-__global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, int nparts, CgState* st) {
+__global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, int nparts, CgState* st,
+                                                          const InstDesc* insts) {
+  if (insts) {
+    part = insts[blockIdx.x].cg.part_out;
+    st = insts[blockIdx.x].cg.st;
+  }
   if (st->done) return;
   double2 a = make_double2(0, 0), b = make_double2(0, 0);
   for (int i = threadIdx.x; i < nparts; i += kRedThreads) {
@@ -407,13 +417,15 @@ hipError_t launch_cg_p(double2* p, const double2* r, long long len, CgState* st,
   return hipGetLastError();
 }
 
-hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_cgf_check, dim3(1), dim3(kRedThreads), 0, s, part_in, nparts, st);
+hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipStream_t s,
+                            const InstDesc* insts, int ninst) {
+  hipLaunchKernelGGL(k_cgf_check, dim3(ninst), dim3(kRedThreads), 0, s, part_in, nparts, st, insts);
   return hipGetLastError();
 }
 
-hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_cgf_step, dim3(1), dim3(kRedThreads), 0, s, part_out, nparts, st);
+hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s,
+                           const InstDesc* insts, int ninst) {
+  hipLaunchKernelGGL(k_cgf_step, dim3(ninst), dim3(kRedThreads), 0, s, part_out, nparts, st, insts);
   return hipGetLastError();
 }
 

@@ -42,7 +42,14 @@ struct Split {
 // p fastest.  LDS tile[(e) * P + p], e = n2 + N2 k1.
 template <int N1, int N2, int S>
 __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2* __restrict__ fld,
-                                             int P, int post_twist, int pre_twist, const int* skip) {
+                                             int P, int post_twist, int pre_twist, const int* skip,
+                                             const InstDesc* __restrict__ insts) {
+  if (insts) {
+    const InstDesc& d = insts[blockIdx.z];
+    t = d.t;
+    fld = d.fld;
+    skip = d.skip;
+  }
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
   constexpr int D = Split<N1, N2>::D;
@@ -101,7 +108,15 @@ __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2
 // ------------------------------------------------------ z pass with medium
 template <int N1, int N2>
 __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med,
-                                                double2* __restrict__ fld, int P, const int* skip) {
+                                                double2* __restrict__ fld, int P, const int* skip,
+                                                const InstDesc* __restrict__ insts) {
+  if (insts) {
+    const InstDesc& d = insts[blockIdx.z];
+    t = d.t;
+    med = d.med;
+    fld = d.fld;
+    skip = d.skip;
+  }
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
   constexpr int D = Split<N1, N2>::D;
@@ -195,7 +210,16 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
 template <int N1, int N2, int PART, bool CG = false>
 __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const double2* __restrict__ y,
                                                       double2* __restrict__ fld, int R,
-                                                      const int* skip, CgFuse cg = CgFuse{}) {
+                                                      const int* skip, CgFuse cg,
+                                                      const InstDesc* __restrict__ insts) {
+  if (insts) {
+    const InstDesc& d = insts[blockIdx.z];
+    t = d.t;
+    y = d.vin;
+    fld = d.fld;
+    skip = d.skip;
+    cg = d.cg;
+  }
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
   constexpr int NP = N + 1;
@@ -304,7 +328,16 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
 template <int N1, int N2, int PART, bool CG = false>
 __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
                                                      double2* __restrict__ out, int R,
-                                                     const int* skip, CgFuse cg = CgFuse{}) {
+                                                     const int* skip, CgFuse cg,
+                                                     const InstDesc* __restrict__ insts) {
+  if (insts) {
+    const InstDesc& d = insts[blockIdx.z];
+    t = d.t;
+    fld = d.fld;
+    out = CG ? d.cg.q : d.vout;
+    skip = d.skip;
+    cg = d.cg;
+  }
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
   constexpr int NP = N + 1;
@@ -473,36 +506,38 @@ bool fast_axis(int N) {
 }
 
 hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int nf, double2* fld,
-                          int post_twist, int pre_twist, const int* skip, hipStream_t s) {
+                          int post_twist, int pre_twist, const int* skip, hipStream_t s,
+                          const InstDesc* insts, int ninst) {
   const int N = axis == 1 ? g.n2 : g.n3;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
   const int P = pick_cols(g.n1, 256 / cfg.N2 < 16 ? 256 / cfg.N2 : 16);
   const long long other = (axis == 1) ? g.n3 : g.n2;
-  const dim3 grid((unsigned)((g.n1 / P) * other), (unsigned)nf);
+  const dim3 grid((unsigned)((g.n1 / P) * other), (unsigned)nf, (unsigned)ninst);
   const dim3 block(P * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + N * P);
 #define L_YZ(A, B)                                                                                   \
   if (dir > 0)                                                                                       \
     hipLaunchKernelGGL((k_fyz<A, B, +1>), grid, block, lds, s, g, t, axis, fld, P, post_twist,       \
-                       pre_twist, skip);                                                             \
+                       pre_twist, skip, insts);                                                      \
   else                                                                                               \
     hipLaunchKernelGGL((k_fyz<A, B, -1>), grid, block, lds, s, g, t, axis, fld, P, post_twist,       \
-                       pre_twist, skip);
+                       pre_twist, skip, insts);
   NSF_FAST_SWITCH(N, L_YZ)
 #undef L_YZ
   return hipGetLastError();
 }
 
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
-                             int P_want, const int* skip, hipStream_t s) {
+                             int P_want, const int* skip, hipStream_t s, const InstDesc* insts,
+                             int ninst) {
   const int N = g.n3;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
   int P = pick_cols(g.n1, P_want);
   while (P > 1 && (6 * P * cfg.N2 > 384 || (size_t)(N + 6 * N * P) * 16 > lds_limit())) P /= 2;
   if (6 * P * cfg.N2 > 384) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((g.n1 / P) * g.n2));
+  const dim3 grid((unsigned)((g.n1 / P) * g.n2), 1, (unsigned)ninst);
   const dim3 block(6 * P * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * N * P);
   // Workgroups above 64 KiB of LDS opt in once per kernel.
@@ -512,14 +547,14 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     if (e != hipSuccess) return e;                                                                  \
   }                                                                                                 \
-  hipLaunchKernelGGL((k_fz_mid<A, B>), grid, block, lds, s, g, t, med, fld, P, skip);
+  hipLaunchKernelGGL((k_fz_mid<A, B>), grid, block, lds, s, g, t, med, fld, P, skip, insts);
   NSF_FAST_SWITCH(N, L_MID)
 #undef L_MID
   return hipGetLastError();
 }
 
 hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, const double2* y, double2* fld,
-                                   const int* skip, hipStream_t s) {
+                                   const int* skip, hipStream_t s, const InstDesc* insts, int ninst) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -528,23 +563,27 @@ hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, con
   while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
   if (F * R * cfg.N2 > 384) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
-  const dim3 grid((unsigned)((rows + R - 1) / R));
+  const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+  const CgFuse none{};
 #define L_XI(A, B)                                                                                    \
   if (part == kPartBoth)                                                                              \
-    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth>), grid, block, lds, s, g, t, y, fld, R, skip); \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth>), grid, block, lds, s, g, t, y, fld, R, skip,  \
+                       none, insts);                                                                  \
   else if (part == kPartP)                                                                            \
-    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartP>), grid, block, lds, s, g, t, y, fld, R, skip);    \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartP>), grid, block, lds, s, g, t, y, fld, R, skip,     \
+                       none, insts);                                                                  \
   else                                                                                                \
-    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartQ>), grid, block, lds, s, g, t, y, fld, R, skip);
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartQ>), grid, block, lds, s, g, t, y, fld, R, skip,     \
+                       none, insts);
   NSF_FAST_SWITCH(N, L_XI)
 #undef L_XI
   return hipGetLastError();
 }
 
 hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld, double2* out,
-                                  const int* skip, hipStream_t s) {
+                                  const int* skip, hipStream_t s, const InstDesc* insts, int ninst) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -553,16 +592,20 @@ hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, cons
   while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
   if (F * R * cfg.N2 > 384) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
-  const dim3 grid((unsigned)((rows + R - 1) / R));
+  const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+  const CgFuse none{};
 #define L_XF(A, B)                                                                                     \
   if (part == kPartBoth)                                                                               \
-    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth>), grid, block, lds, s, g, t, fld, out, R, skip); \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth>), grid, block, lds, s, g, t, fld, out, R, skip,  \
+                       none, insts);                                                                   \
   else if (part == kPartP)                                                                             \
-    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartP>), grid, block, lds, s, g, t, fld, out, R, skip);    \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartP>), grid, block, lds, s, g, t, fld, out, R, skip,     \
+                       none, insts);                                                                   \
   else                                                                                                 \
-    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartQ>), grid, block, lds, s, g, t, fld, out, R, skip);
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartQ>), grid, block, lds, s, g, t, fld, out, R, skip,     \
+                       none, insts);
   NSF_FAST_SWITCH(N, L_XF)
 #undef L_XF
   return hipGetLastError();
@@ -579,7 +622,8 @@ int fast_x_rows(const Geom& g) {
 }
 
 hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg, double2* fld,
-                                const int* skip, int* nparts, hipStream_t s) {
+                                const int* skip, int* nparts, hipStream_t s, const InstDesc* insts,
+                                int ninst) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -587,20 +631,21 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
   while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
   if (6 * R * cfg.N2 > 384) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
-  const dim3 grid((unsigned)((rows + R - 1) / R));
+  const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   *nparts = (int)grid.x;
   const dim3 block(6 * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
 #define L_CGI(A, B)                                                                                  \
   hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true>), grid, block, lds, s, g, t,             \
-                     (const double2*)nullptr, fld, R, skip, cg);
+                     (const double2*)nullptr, fld, R, skip, cg, insts);
   NSF_FAST_SWITCH(N, L_CGI)
 #undef L_CGI
   return hipGetLastError();
 }
 
 hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
-                               const int* skip, int* nparts, hipStream_t s) {
+                               const int* skip, int* nparts, hipStream_t s, const InstDesc* insts,
+                               int ninst) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -608,13 +653,13 @@ hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg,
   while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
   if (6 * R * cfg.N2 > 384) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
-  const dim3 grid((unsigned)((rows + R - 1) / R));
+  const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   *nparts = (int)grid.x;
   const dim3 block(6 * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
 #define L_CGL(A, B)                                                                                  \
   hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true>), grid, block, lds, s, g, t, fld, cg.q,   \
-                     R, skip, cg);
+                     R, skip, cg, insts);
   NSF_FAST_SWITCH(N, L_CGL)
 #undef L_CGL
   return hipGetLastError();

@@ -1,0 +1,597 @@
+// Invert Lanczos for B_r y = theta A_r y (Thm 4.2; Sec. 4.2; Algorithm 1
+// step 5), for one instance or many in lock step.
+//
+// The operator A_r^{-1} B_r is self-adjoint in the A_r inner product and its
+// largest eigenvalues theta are the inverses of the smallest positive omega.
+// The basis V is kept A_r-orthonormal together with A_r V (classical
+// Gram-Schmidt; a second pass only when the first removed more than half of
+// the A-norm squared), and the projected matrix H = V^* B_r V is formed
+// exactly from B_r applied to each new basis vector, so Ritz values are exact
+// Rayleigh quotients of the pencil even though the inner CG solves are
+// inexact.  After m expansions the basis is compressed to the best Ritz
+// vectors plus the last Lanczos vector (thick restart).
+//
+// Many instances (k-points, grids, media) advance together: every CG
+// iteration and every A_r apply is one launch per group of instances with
+// the same grid (the instance is the grid's z index), each instance carrying
+// its own convergence flag, and the host synchronises once per phase for the
+// whole batch.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "nsf_internal.h"
+
+namespace nsf {
+namespace {
+
+struct Run {
+  nsf_plan p = nullptr;
+  int nev = 0, m = 0, kkeep = 0, max_restarts = 0;
+  double res_tol = 0, cg_rtol = 0;
+  unsigned long long seed = 0;
+  long long len = 0;
+  double2 *V = nullptr, *AV = nullptr, *w = nullptr, *z = nullptr, *bv = nullptr;
+  std::vector<double2> H;
+  int nb = 0;
+  std::vector<double> theta, eta;
+  std::vector<double2> Sk;
+  nsf_stats st{};
+  bool finished = false, converged = false;
+  int status = NSF_OK;
+  double2& Hat(int i, int j) { return H[(size_t)i * (m + 1) + j]; }
+};
+
+// Instances sharing one grid shape and pass configuration.
+struct Group {
+  std::vector<Run*> runs;
+  std::vector<Run*> act;   // unfinished runs
+  bool fast = false;       // batched register passes usable
+  InstDesc* d_desc = nullptr;   // [act CG descriptors | act apply descriptors]
+  InstDesc* h_desc = nullptr;   // pinned staging
+  int cap = 0;
+};
+
+// Enqueue sum conj(x) y into d_res[slot] and copy it to h_res[slot].
+int dot_async(nsf_plan p, const double2* x, const double2* y, long long len, int slot) {
+  NSF_HIP(p, launch_dot_partials(x, y, len, p->d_partial, nullptr, p->stream));
+  NSF_HIP(p, launch_reduce_partials(p->d_partial, reduce_parts_for(len), p->d_res + slot, p->stream));
+  NSF_HIP(p, hipMemcpyAsync(p->h_res + slot, p->d_res + slot, sizeof(double2), hipMemcpyDeviceToHost,
+                            p->stream));
+  return NSF_OK;
+}
+
+InstDesc desc_of(Run* r, bool cg) {
+  nsf_plan p = r->p;
+  InstDesc d{};
+  d.t = p->tabs;
+  d.med = medium_view(p);
+  d.fld = p->d_fields;
+  if (cg) {
+    d.skip = &p->d_state->done;
+    d.cg = cg_fuse_of(p, r->w);
+  } else {
+    d.vin = r->w;
+    d.vout = r->z;
+  }
+  return d;
+}
+
+int upload_descs(Group& G, hipStream_t s) {
+  G.act.clear();
+  for (Run* r : G.runs)
+    if (!r->finished) G.act.push_back(r);
+  const int na = (int)G.act.size();
+  if (!G.fast || na == 0) return NSF_OK;
+  for (int i = 0; i < na; ++i) {
+    G.h_desc[i] = desc_of(G.act[i], true);
+    G.h_desc[na + i] = desc_of(G.act[i], false);
+  }
+  const hipError_t e = hipMemcpyAsync(G.d_desc, G.h_desc, sizeof(InstDesc) * 2 * na, hipMemcpyHostToDevice, s);
+  return hip_check(G.act[0]->p, e, "descriptor upload");
+}
+
+// z = A_r w for every unfinished run.
+int apply_all(std::vector<Group>& groups, hipStream_t s) {
+  for (Group& G : groups) {
+    const int na = (int)G.act.size();
+    if (na == 0) continue;
+    if (!G.fast) {
+      for (Run* r : G.act) {
+        const int rc = apply_Ar_dev(r->p, r->w, r->z, nullptr);
+        if (rc) return rc;
+      }
+      continue;
+    }
+    nsf_plan p0 = G.act[0]->p;
+    const Geom& g = p0->geom;
+    const InstDesc* d = G.d_desc + na;
+    NSF_HIP(p0, launch_fast_x_inv_synth(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_x_fwd_proj(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na));
+  }
+  return NSF_OK;
+}
+
+// w = A_r^{-1} bv by CG for every unfinished run, all advancing together.
+int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s) {
+  for (Run* r : act) {
+    nsf_plan p = r->p;
+    NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, p->d_cg + r->len, r->len, p->d_partial, p->d_state,
+                              r->cg_rtol, 5000, s));
+  }
+  std::vector<double> rr_prev(act.size(), -1.0);
+  std::vector<int> it_prev(act.size(), 0);
+  int chunk = 4;
+  for (;;) {
+    for (int c = 0; c < chunk; ++c) {
+      for (Group& G : groups) {
+        const int na = (int)G.act.size();
+        if (na == 0) continue;
+        if (!G.fast) {
+          for (Run* r : G.act) {
+            const int rc = cg_iteration(r->p, r->w, cg_fusable(r->p));
+            if (rc) return rc;
+          }
+          continue;
+        }
+        nsf_plan p0 = G.act[0]->p;
+        const Geom& g = p0->geom;
+        const InstDesc* d = G.d_desc;
+        const CgFuse none{};
+        int np1 = 0, np5 = 0;
+        NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na));
+        NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
+        NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
+        NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na));
+        NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
+        NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na));
+        NSF_HIP(p0, launch_cgf_step(nullptr, np5, nullptr, s, d, na));
+      }
+    }
+    for (Run* r : act)
+      NSF_HIP(r->p, hipMemcpyAsync(r->p->h_state, r->p->d_state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    NSF_HIP(act[0]->p, hipStreamSynchronize(s));
+    bool all = true;
+    int next = 1;
+    for (size_t i = 0; i < act.size(); ++i) {
+      const CgState& h = *act[i]->p->h_state;
+      if (h.done) continue;
+      all = false;
+      next = std::max(next, cg_predict(h, rr_prev[i], it_prev[i], cg_fusable(act[i]->p)));
+      rr_prev[i] = h.rr;
+      it_prev[i] = h.iter;
+    }
+    if (all) break;
+    chunk = next;
+  }
+  for (Run* r : act) {
+    const CgState& h = *r->p->h_state;
+    r->st.cg_solves += 1;
+    r->st.cg_iters_total += h.iter;
+    r->st.matvecs += h.iter;
+    if (h.status == NSF_E_BREAKDOWN)
+      return set_error(r->p, NSF_E_BREAKDOWN, "CG breakdown: p^* A_r p <= 0 or not finite");
+  }
+  return NSF_OK;
+}
+
+// Gram-Schmidt pass of (w, z) against V[0..nb) in the A_r inner product.
+int ortho_pass(Run* r) {
+  nsf_plan p = r->p;
+  hipStream_t s = p->stream;
+  NSF_HIP(p, launch_multi_dot(r->AV, r->len, r->nb, r->w, r->len, p->d_partial, p->d_coef, s));
+  NSF_HIP(p, launch_multi_axpy(r->V, r->len, r->nb, p->d_coef, r->w, r->len, s));
+  NSF_HIP(p, launch_multi_axpy(r->AV, r->len, r->nb, p->d_coef, r->z, r->len, s));
+  r->st.ortho_passes += 1;
+  return dot_async(p, r->w, r->z, r->len, 1);
+}
+
+// Enqueue V[j] = w / sqrt(nrm2), A V[j] = z / sqrt(nrm2), bv = B_r V[j] and the
+// H column V^* bv (copied to h_res[64 ..]).
+int admit_enqueue(Run* r, int j, double nrm2) {
+  nsf_plan p = r->p;
+  hipStream_t s = p->stream;
+  if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+    return set_error(p, NSF_E_BREAKDOWN, "A_r-norm of a new basis vector is not positive");
+  const double sc = 1.0 / std::sqrt(nrm2);
+  NSF_HIP(p, launch_scale_copy(r->w, r->V + (size_t)j * r->len, sc, 0.0, r->len, s));
+  NSF_HIP(p, launch_scale_copy(r->z, r->AV + (size_t)j * r->len, sc, 0.0, r->len, s));
+  NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, r->V + (size_t)j * r->len, r->bv, nullptr, s));
+  NSF_HIP(p, launch_multi_dot(r->V, r->len, j + 1, r->bv, r->len, p->d_partial, p->d_coef, s));
+  NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_coef, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+  return NSF_OK;
+}
+
+void admit_finish(Run* r, int j) {
+  const double2* hc = r->p->h_res + 64;
+  for (int i = 0; i <= j; ++i) {  // H[i][j] = V_i^* B V_j
+    r->Hat(i, j) = hc[i];
+    r->Hat(j, i) = cconj(hc[i]);
+  }
+  r->Hat(j, j).y = 0.0;
+}
+
+// Rayleigh-Ritz on V[0..m) of one run: rotate to the kkeep best Ritz
+// vectors, enqueue the residual norms of the wanted pairs.
+int restart_enqueue(Run* r) {
+  nsf_plan p = r->p;
+  hipStream_t s = p->stream;
+  const int m = r->m, kk = r->kkeep;
+  std::vector<double2> Hm((size_t)m * m), S((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) Hm[(size_t)i * m + j] = r->Hat(i, j);
+  std::vector<double> wv(m);
+  hermitian_eig(m, Hm.data(), wv.data(), S.data());
+  r->Sk.assign((size_t)m * kk, make_double2(0, 0));
+  for (int c = 0; c < kk; ++c) {  // descending theta: column c of Sk is eigenvector m-1-c
+    r->theta[c] = wv[m - 1 - c];
+    for (int i = 0; i < m; ++i) r->Sk[(size_t)c * m + i] = S[(size_t)i * m + (m - 1 - c)];
+  }
+  NSF_HIP(p, hipMemcpyAsync(p->d_small, r->Sk.data(), sizeof(double2) * (size_t)m * kk, hipMemcpyHostToDevice, s));
+  NSF_HIP(p, launch_rotate(r->V, r->len, m, kk, p->d_small, r->len, s));
+  NSF_HIP(p, launch_rotate(r->AV, r->len, m, kk, p->d_small, r->len, s));
+  for (int i = 0; i < r->nev; ++i) {
+    NSF_HIP(p, launch_residual_norms(p->geom, p->tabs, r->V + (size_t)i * r->len, r->AV + (size_t)i * r->len,
+                                     r->theta[i], p->d_partial, reinterpret_cast<double*>(p->d_res + 64 + i), s));
+  }
+  NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_res + 64, sizeof(double2) * r->nev, hipMemcpyDeviceToHost, s));
+  // hermitian_eig reads the host copy of the Sk buffer asynchronously: keep it
+  // alive in r->Sk until the next synchronisation.
+  return NSF_OK;
+}
+
+// After the restart's synchronisation: residuals, new projected matrix for
+// [Ritz vectors, V[m]], move V[m] next to the Ritz vectors.
+int restart_finish(Run* r) {
+  nsf_plan p = r->p;
+  hipStream_t s = p->stream;
+  const int m = r->m, kk = r->kkeep;
+  bool all = true;
+  for (int i = 0; i < r->nev; ++i) {
+    const double2 r2 = p->h_res[64 + i];
+    r->eta[i] = std::sqrt(r2.x) / (std::fabs(r->theta[i]) * std::sqrt(r2.y));
+    if (!(r->theta[i] > 0.0) || !(r->eta[i] <= r->res_tol)) all = false;
+  }
+  std::vector<double2> row(kk);
+  for (int c = 0; c < kk; ++c) {
+    double2 acc = make_double2(0, 0);
+    for (int i = 0; i < m; ++i) acc = cadd(acc, cmul(r->Hat(m, i), r->Sk[(size_t)c * m + i]));
+    row[c] = acc;
+  }
+  const double2 hmm = r->Hat(m, m);
+  std::fill(r->H.begin(), r->H.end(), make_double2(0, 0));
+  for (int c = 0; c < kk; ++c) {
+    r->Hat(c, c) = make_double2(r->theta[c], 0);
+    r->Hat(kk, c) = row[c];
+    r->Hat(c, kk) = cconj(row[c]);
+  }
+  r->Hat(kk, kk) = hmm;
+  NSF_HIP(p, hipMemcpyAsync(r->V + (size_t)kk * r->len, r->V + (size_t)m * r->len, sizeof(double2) * r->len,
+                            hipMemcpyDeviceToDevice, s));
+  NSF_HIP(p, hipMemcpyAsync(r->AV + (size_t)kk * r->len, r->AV + (size_t)m * r->len, sizeof(double2) * r->len,
+                            hipMemcpyDeviceToDevice, s));
+  r->nb = kk + 1;
+  if (all) {
+    r->converged = true;
+    r->finished = true;
+  } else {
+    r->st.restarts += 1;
+    if (r->st.restarts > r->max_restarts) r->finished = true;
+  }
+  return NSF_OK;
+}
+
+// Replace w by a fresh random direction orthogonal to the basis (the Krylov
+// space became invariant).  Synchronous; rare.
+int refresh_direction(Run* r, hipStream_t s) {
+  nsf_plan p = r->p;
+  NSF_HIP(p, launch_randn(r->w, r->len, r->seed + 7919ULL * (r->st.lanczos_steps + 1), s));
+  int rc = apply_Ar_dev(p, r->w, r->z, nullptr);
+  if (rc) return rc;
+  r->st.matvecs += 1;
+  for (int pass = 0; pass < 2; ++pass) {
+    rc = ortho_pass(r);
+    if (rc) return rc;
+  }
+  NSF_HIP(p, hipStreamSynchronize(s));
+  return NSF_OK;
+}
+
+// Run every instance to convergence (or its restart cap) in lock step.
+int run_engine(std::vector<Run*>& runs, hipStream_t s) {
+  // groups of equal grid shape and pass configuration
+  std::map<std::tuple<int, int, int, double, double, int, int>, int> key;
+  std::vector<Group> groups;
+  for (Run* r : runs) {
+    const Geom& g = r->p->geom;
+    auto k = std::make_tuple(g.n1, g.n2, g.n3, g.alpha, g.beta, r->p->opt_fft_path, r->p->opt_mid_cols);
+    if (!key.count(k)) {
+      key[k] = (int)groups.size();
+      groups.emplace_back();
+    }
+    groups[key[k]].runs.push_back(r);
+  }
+  int rc = NSF_OK;
+  for (Group& G : groups) {
+    nsf_plan p0 = G.runs[0]->p;
+    const Geom& g = p0->geom;
+    G.fast = p0->opt_fft_path == 0 && fast_axis(g.n1) && fast_axis(g.n2) && fast_axis(g.n3) &&
+             cg_fusable(p0) && G.runs.size() > 1;
+    G.cap = (int)G.runs.size();
+    if (G.fast) {
+      NSF_HIP(p0, hipMalloc(&G.d_desc, sizeof(InstDesc) * 2 * G.cap));
+      NSF_HIP(p0, hipHostMalloc(&G.h_desc, sizeof(InstDesc) * 2 * G.cap));
+    }
+  }
+  auto release = [&]() {
+    hipStreamSynchronize(s);
+    for (Group& G : groups) {
+      if (G.d_desc) hipFree(G.d_desc);
+      if (G.h_desc) hipHostFree(G.h_desc);
+    }
+  };
+  auto fail = [&](int code) {
+    release();
+    return code;
+  };
+  for (Group& G : groups)
+    if ((rc = upload_descs(G, s))) return fail(rc);
+
+  // start vectors: seeded complex normal, A_r-normalised
+  for (Run* r : runs) NSF_HIP(r->p, launch_randn(r->w, r->len, r->seed, s));
+  if ((rc = apply_all(groups, s))) return fail(rc);
+  for (Run* r : runs) {
+    r->st.matvecs += 1;
+    if ((rc = dot_async(r->p, r->w, r->z, r->len, 0))) return fail(rc);
+  }
+  NSF_HIP(runs[0]->p, hipStreamSynchronize(s));
+  for (Run* r : runs)
+    if ((rc = admit_enqueue(r, 0, r->p->h_res[0].x))) return fail(rc);
+  NSF_HIP(runs[0]->p, hipStreamSynchronize(s));
+  for (Run* r : runs) {
+    admit_finish(r, 0);
+    r->nb = 1;
+  }
+
+  for (;;) {
+    std::vector<Run*> act;
+    for (Run* r : runs)
+      if (!r->finished) act.push_back(r);
+    if (act.empty()) break;
+    // expand: w = A_r^{-1} B_r V[nb-1], z = A_r w
+    if ((rc = cg_all(groups, act, s))) return fail(rc);
+    if ((rc = apply_all(groups, s))) return fail(rc);
+    for (Run* r : act) {
+      r->st.matvecs += 1;
+      if ((rc = dot_async(r->p, r->w, r->z, r->len, 0))) return fail(rc);  // norm before
+      if ((rc = ortho_pass(r))) return fail(rc);
+    }
+    NSF_HIP(act[0]->p, hipStreamSynchronize(s));
+    bool again = false;
+    std::vector<double> before(act.size());
+    for (size_t i = 0; i < act.size(); ++i) {
+      nsf_plan p = act[i]->p;
+      before[i] = p->h_res[0].x;
+      if (p->h_res[1].x <= 0.5 * before[i]) {  // second pass needed
+        before[i] = p->h_res[1].x;
+        if ((rc = ortho_pass(act[i]))) return fail(rc);
+        again = true;
+      }
+    }
+    if (again) NSF_HIP(act[0]->p, hipStreamSynchronize(s));
+    for (size_t i = 0; i < act.size(); ++i) {
+      Run* r = act[i];
+      if (!(r->p->h_res[1].x > 1e-20 * r->p->h_res[0].x)) {
+        if ((rc = refresh_direction(r, s))) return fail(rc);
+      }
+      if ((rc = admit_enqueue(r, r->nb, r->p->h_res[1].x))) return fail(rc);
+    }
+    NSF_HIP(act[0]->p, hipStreamSynchronize(s));
+    for (Run* r : act) {
+      admit_finish(r, r->nb);
+      r->nb += 1;
+      r->st.lanczos_steps += 1;
+    }
+    bool any_restart = false;
+    for (Run* r : act)
+      if (r->nb == r->m + 1) {
+        if ((rc = restart_enqueue(r))) return fail(rc);
+        any_restart = true;
+      }
+    if (!any_restart) continue;
+    NSF_HIP(act[0]->p, hipStreamSynchronize(s));
+    bool changed = false;
+    for (Run* r : act)
+      if (r->nb == r->m + 1) {
+        if ((rc = restart_finish(r))) return fail(rc);
+        changed |= r->finished;
+      }
+    if (changed)
+      for (Group& G : groups)
+        if ((rc = upload_descs(G, s))) return fail(rc);
+  }
+  release();
+  return NSF_OK;
+}
+
+// Prepare one run on plan p (workspace, parameters).
+int make_run(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis, int max_restarts,
+             unsigned long long seed, Run& r) {
+  if (p->medium_kind == kMedNone) return set_error(p, NSF_E_STATE, "no medium set");
+  const long long n = p->geom.n, len = 4 * n;
+  if (nev < 1 || nev > 256 || 2LL * nev >= len) return set_error(p, NSF_E_ARG, "nev out of range");
+  if (!(res_tol > 0.0) || !(cg_rtol > 0.0)) return set_error(p, NSF_E_ARG, "tolerances must be > 0");
+  int m = max_basis > 0 ? max_basis : std::max(3 * nev, nev + 8);
+  if (m < nev + 2) m = nev + 2;
+  if (m > 510) m = 510;
+  if (m >= len) m = (int)len - 1;
+  if (m < nev + 2) return set_error(p, NSF_E_ARG, "grid too small for nev");
+  int rc = ensure_cg(p);
+  if (rc) return rc;
+  rc = ensure_basis(p, (size_t)m + 1);
+  if (rc) return rc;
+  rc = ensure_small(p, (size_t)m * m);
+  if (rc) return rc;
+  r.p = p;
+  r.nev = nev;
+  r.m = m;
+  r.kkeep = std::min(m - 1, nev + (m - nev) / 2);
+  r.max_restarts = max_restarts > 0 ? max_restarts : 1000;
+  r.res_tol = res_tol;
+  r.cg_rtol = cg_rtol;
+  r.seed = seed;
+  r.len = len;
+  r.V = p->d_basis;
+  r.AV = r.V + (size_t)(m + 1) * len;
+  r.w = p->d_cg + 3 * len;
+  r.z = r.w + len;
+  r.bv = r.z + len;
+  r.H.assign((size_t)(m + 1) * (m + 1), make_double2(0, 0));
+  r.theta.assign(m, 0.0);
+  r.eta.assign(nev, INFINITY);
+  return NSF_OK;
+}
+
+void finish_run(Run& r, double* omega, double* resid, nsf_stats* stats, double ms) {
+  int nconv = 0;
+  for (int i = 0; i < r.nev; ++i) {
+    omega[i] = 1.0 / r.theta[i];
+    if (resid) resid[i] = r.eta[i];
+    if (r.eta[i] <= r.res_tol) ++nconv;
+  }
+  r.st.converged = nconv;
+  r.st.cg_iters_avg = r.st.cg_solves ? (double)r.st.cg_iters_total / r.st.cg_solves : 0.0;
+  r.st.bytes_alg = 336.0 * (double)r.p->geom.n * (double)r.st.matvecs;
+  r.st.ms_total = ms;
+  if (stats) *stats = r.st;
+}
+
+}  // namespace
+}  // namespace nsf
+
+using namespace nsf;
+
+// The batch: independent plans (grid, k, medium each) on one stream.
+struct nsf_batch_s {
+  std::vector<nsf_plan> plans;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+};
+
+extern "C" {
+
+int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis, int max_restarts,
+             unsigned long long seed, double* omega_host, nsf_c128* Y_dev, double* resid_host,
+             nsf_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p || !omega_host) return set_error(p, NSF_E_ARG, "NULL argument");
+  Run r;
+  int rc = make_run(p, nev, res_tol, cg_rtol, max_basis, max_restarts, seed, r);
+  if (rc) return rc;
+  std::vector<Run*> runs{&r};
+  rc = run_engine(runs, p->stream);
+  if (rc) return rc;
+  if (Y_dev)
+    NSF_HIP(p, hipMemcpyAsync(Y_dev, r.V, sizeof(double2) * (size_t)nev * r.len, hipMemcpyDeviceToDevice, p->stream));
+  NSF_HIP(p, hipStreamSynchronize(p->stream));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  finish_run(r, omega_host, resid_host, stats, ms);
+  return r.converged ? NSF_OK : NSF_NOT_CONVERGED;
+}
+
+int nsf_batch_create(nsf_batch* out, int count, const int* grids, const double* ks, double a, double alpha,
+                     double beta, void* hip_stream) {
+  if (!out) return set_error(nullptr, NSF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !grids || !ks) return set_error(nullptr, NSF_E_ARG, "bad batch arguments");
+  auto* b = new (std::nothrow) nsf_batch_s();
+  if (!b) return set_error(nullptr, NSF_E_NOMEM, "host allocation failed");
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < count; ++i) {
+    nsf_plan p = nullptr;
+    const int rc = nsf_plan_create(&p, grids[3 * i], grids[3 * i + 1], grids[3 * i + 2], a, ks + 3 * i, alpha,
+                                   beta, hip_stream);
+    if (rc) {
+      const std::string msg = "instance " + std::to_string(i) + ": " + nsf_last_error(nullptr);
+      nsf_batch_destroy(b);
+      return set_error(nullptr, rc, msg);
+    }
+    b->plans.push_back(p);
+  }
+  *out = b;
+  return NSF_OK;
+}
+
+void nsf_batch_destroy(nsf_batch b) {
+  if (!b) return;
+  for (nsf_plan p : b->plans) nsf_plan_destroy(p);
+  delete b;
+}
+
+int nsf_batch_plan(nsf_batch b, int i, nsf_plan* plan) {
+  if (!b || !plan || i < 0 || i >= (int)b->plans.size()) return set_error(nullptr, NSF_E_ARG, "bad batch index");
+  *plan = b->plans[i];
+  return NSF_OK;
+}
+
+int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max_basis, int max_restarts,
+                   unsigned long long seed, double* omega_host, double* resid_host, nsf_stats* stats,
+                   int* wave_size) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!b || !omega_host) return set_error(nullptr, NSF_E_ARG, "NULL argument");
+  const int B = (int)b->plans.size();
+  // Instances run in waves that fit in device memory: fields 6n, CG and
+  // Lanczos vectors 6 x 4n, basis 2 (m+1) x 4n, medium n complex each.
+  const int m = max_basis > 0 ? max_basis : std::max(3 * nev, nev + 8);
+  size_t free_b = 0, total_b = 0;
+  NSF_HIP(b->plans[0], hipMemGetInfo(&free_b, &total_b));
+  double need_max = 0;
+  for (nsf_plan p : b->plans) {
+    const double n = (double)p->geom.n;
+    need_max = std::max(need_max, 16.0 * n * (6 + 24 + 8.0 * (m + 1) + 1) + (64 << 20));
+  }
+  int wave = (int)std::max(1.0, std::floor(0.85 * (double)free_b / need_max));
+  wave = std::min(wave, B);
+  if (wave_size) *wave_size = wave;
+  int worst = NSF_OK;
+  for (int w0 = 0; w0 < B; w0 += wave) {
+    const int w1 = std::min(B, w0 + wave);
+    std::vector<Run> runs(w1 - w0);
+    std::vector<Run*> ptrs;
+    for (int i = w0; i < w1; ++i) {
+      nsf_plan p = b->plans[i];
+      p->stream = b->stream;
+      const int rc = make_run(p, nev, res_tol, cg_rtol, max_basis, max_restarts, seed + 1000003ULL * i, runs[i - w0]);
+      if (rc) return set_error(nullptr, rc, "instance " + std::to_string(i) + ": " + p->last_error);
+      ptrs.push_back(&runs[i - w0]);
+    }
+    const int rc = run_engine(ptrs, b->stream);
+    if (rc) return set_error(nullptr, rc, std::string("batch: ") + ptrs[0]->p->last_error);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = w0; i < w1; ++i) {
+      Run& r = runs[i - w0];
+      finish_run(r, omega_host + (size_t)i * nev, resid_host ? resid_host + (size_t)i * nev : nullptr,
+                 stats ? stats + i : nullptr, ms);
+      if (!r.converged) worst = NSF_NOT_CONVERGED;
+    }
+    // free this wave's Lanczos storage before the next wave
+    if (w1 < B)
+      for (int i = w0; i < w1; ++i) {
+        nsf_plan p = b->plans[i];
+        NSF_HIP(p, hipStreamSynchronize(b->stream));
+        if (p->d_basis) NSF_HIP(p, hipFree(p->d_basis));
+        p->d_basis = nullptr;
+        p->basis_vectors = 0;
+        if (p->d_cg) NSF_HIP(p, hipFree(p->d_cg));
+        p->d_cg = nullptr;
+      }
+  }
+  return worst;
+}
+
+}  // extern "C"

@@ -103,14 +103,20 @@ hipError_t launch_x_fwd_proj(const Geom& g, const AxisPlan& ax, const Tables& t,
 // Register-resident fast path for axis lengths with a two-level split
 // (16, 32, 48, 64, 96, 128, 256); same semantics as the generic launchers.
 bool fast_axis(int N);
+// With insts != nullptr the launch covers ninst instances (grid z) and every
+// pointer argument is ignored in favour of the descriptors.
 hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, const double2* y,
-                                   double2* fld, const int* skip, hipStream_t s);
+                                   double2* fld, const int* skip, hipStream_t s,
+                                   const struct InstDesc* insts = nullptr, int ninst = 1);
 hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int nf, double2* fld,
-                          int post_twist, int pre_twist, const int* skip, hipStream_t s);
+                          int post_twist, int pre_twist, const int* skip, hipStream_t s,
+                          const struct InstDesc* insts = nullptr, int ninst = 1);
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
-                             int P_want, const int* skip, hipStream_t s);
+                             int P_want, const int* skip, hipStream_t s,
+                             const struct InstDesc* insts = nullptr, int ninst = 1);
 hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld,
-                                  double2* out, const int* skip, hipStream_t s);
+                                  double2* out, const int* skip, hipStream_t s,
+                                  const struct InstDesc* insts = nullptr, int ninst = 1);
 
 // Single-wave passes holding E' / H' components per lane (axis lengths 16,
 // 32, 64, 128); same semantics again.
@@ -131,6 +137,7 @@ hipError_t launch_apply_Br(const Geom& g, const Tables& t, const double2* u, dou
 constexpr int kRedBlocks = 1024;       // partial-sum slots for one reduction
 constexpr int kPartialSlots = 131072;  // partial-sum slots of the multi-vector dot (512 x 256)
 constexpr int kCoefSlots = 1024;       // device coefficient vector of the Lanczos steps
+constexpr int kResSlots = 1100;        // reduction results (and host copies of coefficients)
 
 struct CgState {
   double rr;        // r^* r of the current iterate
@@ -150,9 +157,22 @@ struct CgFuse {
   double2* r;
   double2* p;
   double2* q;
-  const CgState* st;
+  CgState* st;
   double* part_in;   // per-workgroup |r|^2 of the first pass
   double* part_out;  // per-workgroup (Re p^*q, |q|^2, Re r^*q) of the last pass
+};
+
+// Per-instance pointers of a batched launch (instances of one grid shape):
+// block index z selects the instance.  Kernels given a descriptor array take
+// every pointer below from it instead of from their own arguments.
+struct InstDesc {
+  Tables t;
+  MediumView med;
+  double2* fld;         // six-field workspace
+  const double2* vin;   // input 4n vector of a plain apply
+  double2* vout;        // output 4n vector of a plain apply
+  const int* skip;      // nonzero: the instance is finished (CG done flag)
+  CgFuse cg;
 };
 
 // First pass of a fused CG iteration: for iter > 0 it forms
@@ -162,15 +182,21 @@ struct CgFuse {
 // number of workgroups through *nparts.
 int fast_x_rows(const Geom& g);
 hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg, double2* fld,
-                                const int* skip, int* nparts, hipStream_t s);
+                                const int* skip, int* nparts, hipStream_t s,
+                                const InstDesc* insts = nullptr, int ninst = 1);
 // Last pass: q = projection of the forward x transform (written to cg.q) and
 // the per-workgroup partial sums of p^*q, |q|^2, r^*q.
 hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
-                               const int* skip, int* nparts, hipStream_t s);
+                               const int* skip, int* nparts, hipStream_t s,
+                               const InstDesc* insts = nullptr, int ninst = 1);
 // Scalar steps of the fused CG: check |r|^2 after the first pass, then alpha,
 // beta from the last pass (|r - alpha q|^2 by expansion).
-hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipStream_t s);
-hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s);
+// Batched forms (insts != nullptr): one workgroup per instance, partials and
+// state taken from insts[i].cg.
+hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipStream_t s,
+                            const InstDesc* insts = nullptr, int ninst = 1);
+hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s,
+                           const InstDesc* insts = nullptr, int ninst = 1);
 
 // partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
 hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,
@@ -243,7 +269,8 @@ struct nsf_plan_s {
   double2* d_cg = nullptr;      // x r p q : 4 x 4n (cg scratch)
   double2* d_partial = nullptr; // kPartialSlots partial sums
   double2* d_coef = nullptr;    // kCoefSlots complex coefficients (multi-dot results)
-  double2* d_res = nullptr;     // 64 complex reduction results
+  double2* d_res = nullptr;     // kResSlots complex reduction results
+  double2* h_res = nullptr;     // pinned host mirror of d_res
   double2* d_small = nullptr;   // small dense matrices (Ritz rotations)
   size_t small_cap = 0;
   nsf::CgState* d_state = nullptr;
@@ -284,6 +311,11 @@ hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip);
 hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip);
 int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
                  double* relres, long long* matvecs);
+int ensure_cg(nsf_plan p);
+bool cg_fusable(nsf_plan p);
+CgFuse cg_fuse_of(nsf_plan p, double2* x);
+int cg_iteration(nsf_plan p, double2* x, bool fused);
+int cg_predict(const CgState& h, double rr_prev, int it_prev, bool fused);
 int ensure_basis(nsf_plan p, size_t vectors);
 int ensure_small(nsf_plan p, size_t count);
 int hermitian_eig(int m, const double2* H, double* w, double2* V);

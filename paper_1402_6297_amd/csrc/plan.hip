@@ -65,9 +65,10 @@ int ensure_device(nsf_plan p) {
   p->tabs.twist = p->d_tables + ntab;
   p->tabs.tw = p->d_tables + 2 * ntab;
   NSF_HIP(p, hipMalloc(&p->d_fields, sizeof(double2) * 6 * (size_t)g.n));
-  NSF_HIP(p, hipMalloc(&p->d_partial, sizeof(double2) * (size_t)(kPartialSlots + kCoefSlots + 64)));
+  NSF_HIP(p, hipMalloc(&p->d_partial, sizeof(double2) * (size_t)(kPartialSlots + kCoefSlots + kResSlots)));
   p->d_coef = p->d_partial + kPartialSlots;
   p->d_res = p->d_coef + kCoefSlots;
+  NSF_HIP(p, hipHostMalloc(&p->h_res, sizeof(double2) * kResSlots));
   NSF_HIP(p, hipMalloc(&p->d_state, sizeof(CgState)));
   NSF_HIP(p, hipHostMalloc(&p->h_state, sizeof(CgState)));
   NSF_HIP(p, hipMalloc(&p->d_flags, sizeof(int) * 16));
@@ -287,6 +288,7 @@ void nsf_plan_destroy(nsf_plan p) {
     hipHostFree(p->h_state);
     hipFree(p->d_flags);
     hipHostFree(p->h_flags);
+    hipHostFree(p->h_res);
     if (p->d_medium) hipFree(p->d_medium);
     if (p->d_cg) hipFree(p->d_cg);
     if (p->d_basis) hipFree(p->d_basis);

@@ -37,6 +37,7 @@ EXPORTED = [
     "nsf_apply_Pr", "nsf_apply_Qr", "nsf_apply_PrH", "nsf_apply_QrH",
     "nsf_apply_Ar", "nsf_apply_Br", "nsf_profile_Ar", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
     "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
+    "nsf_batch_create", "nsf_batch_plan", "nsf_batch_eigs", "nsf_batch_destroy",
 ]
 
 
@@ -101,6 +102,11 @@ def lib():
         "nsf_eig_grad": (I, [P, I, DP, VP, DP, VP, VP]),
         "nsf_hermitian_eig": (I, [I, VP, DP, VP]),
         "nsf_device_info": (I, [I, C.POINTER(nsf_device)]),
+        "nsf_batch_create": (I, [C.POINTER(P), I, VP, VP, D, D, D, VP]),
+        "nsf_batch_plan": (I, [P, I, C.POINTER(P)]),
+        "nsf_batch_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, DP, C.POINTER(nsf_stats),
+                               C.POINTER(I)]),
+        "nsf_batch_destroy": (None, [P]),
         "nsf_status_string": (C.c_char_p, [I]),
         "nsf_last_error": (C.c_char_p, [P]),
     }
@@ -273,6 +279,41 @@ def nsf_device_info(device=0):
     return d.as_dict()
 
 
+def nsf_batch_create(grids, ks, a=1.0, alpha=-1.0, beta=2.0, stream=None):
+    g = np.ascontiguousarray(np.asarray(grids, dtype=np.int32).reshape(-1, 3))
+    k = np.ascontiguousarray(np.asarray(ks, dtype=np.float64).reshape(-1, 3))
+    if len(g) != len(k):
+        raise ValueError("grids and ks differ in length")
+    b = C.c_void_p()
+    s = current_stream() if stream is None else stream
+    _check(lib().nsf_batch_create(C.byref(b), len(g), C.c_void_p(g.ctypes.data), C.c_void_p(k.ctypes.data),
+                                  float(a), float(alpha), float(beta), C.c_void_p(s)))
+    return b
+
+
+def nsf_batch_plan(batch, i):
+    p = C.c_void_p()
+    _check(lib().nsf_batch_plan(batch, int(i), C.byref(p)))
+    return p
+
+
+def nsf_batch_eigs(batch, count, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, max_restarts=0, seed=0):
+    """Returns (status, omega[count, nev], resid[count, nev], list of stats dicts, wave size)."""
+    omega = np.zeros((count, nev))
+    resid = np.zeros((count, nev))
+    st = (nsf_stats * count)()
+    wave = C.c_int()
+    status = _check(lib().nsf_batch_eigs(batch, int(nev), float(res_tol), float(cg_rtol), int(max_basis),
+                                         int(max_restarts), C.c_ulonglong(seed),
+                                         omega.ctypes.data_as(C.POINTER(C.c_double)),
+                                         resid.ctypes.data_as(C.POINTER(C.c_double)), st, C.byref(wave)))
+    return status, omega, resid, [x.as_dict() for x in st], wave.value
+
+
+def nsf_batch_destroy(batch):
+    lib().nsf_batch_destroy(batch)
+
+
 def nsf_status_string(status):
     return lib().nsf_status_string(int(status)).decode()
 
@@ -282,6 +323,44 @@ def nsf_last_error(plan=None):
 
 
 # ------------------------------------------------------------ convenience
+
+class Batch:
+    """Owns an ``nsf_batch`` of instances given as (grid, k) pairs."""
+
+    def __init__(self, grids, ks, a=1.0, alpha=-1.0, beta=2.0, stream=None):
+        self.count = len(grids)
+        self.grids = [tuple(int(x) for x in g) for g in grids]
+        self.handle = nsf_batch_create(grids, ks, a, alpha, beta, stream)
+
+    def plan(self, i):
+        return nsf_batch_plan(self.handle, i)
+
+    def set_chiral(self, i, eps, gamma):
+        return nsf_set_medium_chiral(self.plan(i), eps, gamma)
+
+    def set_pseudochiral(self, i, axis_a, axis_b, eps, gamma):
+        return nsf_set_medium_pseudochiral(self.plan(i), axis_a, axis_b, eps, gamma)
+
+    def eigs(self, nev, **kw):
+        return nsf_batch_eigs(self.handle, self.count, nev, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            nsf_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
 
 class Plan:
     """Owns an ``nsf_plan``; frees it on ``close()`` / garbage collection."""

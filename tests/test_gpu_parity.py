@@ -328,3 +328,46 @@ def test_gradient_matches_oracle_4():
     ref_g = (w[:, None] * dg_ref).sum(axis=0)
     assert rel(de, ref_e) < 1e-8
     assert rel(dg, ref_g) < 1e-8
+
+
+# ------------------------------------------------------------------ batches
+
+def test_batch_matches_single_solves():
+    """Batched schedule (same-grid groups share launches, per-instance CG masks)
+    gives the per-instance eigenvalues; one instance is the golden 16^3 case."""
+    g16 = json.load(open(os.path.join(HERE, "golden", "config1_16.json")))
+    insts = [((16, 16, 16), (0.1, 0.2, 0.3), "sphere"),
+             ((16, 16, 16), (0.25, 0.0, 0.0), "sphere"),
+             ((16, 16, 16), (0.5, 0.5, 0.1), "rods"),
+             ((8, 8, 8), (0.3, 0.1, 0.2), "sphere"),
+             ((32, 32, 32), (0.2, 0.2, 0.2), "sphere")]
+    nev = 6
+    with nsf.Batch([g for g, _, _ in insts], [k for _, k, _ in insts]) as B:
+        media_in = []
+        for i, (g, k, kind) in enumerate(insts):
+            if kind == "sphere":
+                eps, gam = media.sphere_chiral(*g)
+                B.set_chiral(i, eps, gam)
+                media_in.append((eps, gam, None))
+            else:
+                eps, gam = media.rods_pseudochiral(*g, radius=0.3)
+                B.set_pseudochiral(i, 0, 1, eps, gam)
+                media_in.append((eps, gam, (0, 1)))
+        st, om, res, stats, wave = B.eigs(nev, res_tol=1e-9, cg_rtol=1e-11, seed=3)
+    assert st == nsf.NSF_OK and res.max() <= 1e-9 and wave >= 1
+    assert np.abs(om[0] - np.array(g16["omega"][:nev])).max() <= 1e-10 * om[0].max()
+    for i, (g, k, kind) in enumerate(insts):
+        eps, gam, pair = media_in[i]
+        with nsf.Plan(g, k) as P:
+            _set(P, eps, gam, pair)
+            st1, om1, res1, _ = P.eigs(nev, res_tol=1e-9, cg_rtol=1e-11, seed=3 + 1000003 * i)
+        assert st1 == nsf.NSF_OK
+        assert np.abs(om[i] - om1).max() <= 1e-10 * om1.max(), (i, om[i], om1)
+        assert stats[i]["converged"] == nev
+
+
+def test_batch_rejects_bad_instance():
+    with pytest.raises(nsf.NsfError) as e:
+        nsf.Batch([(16, 16, 16), (16, 16, 16)], [(0.1, 0.2, 0.3), (0.0, 0.0, 0.0)])
+    assert e.value.status == nsf.NSF_E_KPOINT
+    assert "instance 1" in nsf.nsf_last_error(None)
