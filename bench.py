@@ -48,6 +48,70 @@ def make_medium(w):
     return media.rods_pseudochiral(n1)
 
 
+def batch_instances(name):
+    """(grids, ks, media, nev) of the batched workloads."""
+    from paper_1402_6297_amd import media
+
+    if name == "kpath128":  # Gamma-X-M-Gamma-R, 10 per segment, x-y rods at 128^3
+        ks = media.kpath_gxmgr(10)
+        eps, gam = media.rods_pseudochiral(128)
+        return [(128, 128, 128)] * len(ks), ks, [("pseudo", eps, gam)] * len(ks), 10
+    if name.startswith("uneven"):  # mixed 48..128^3 chiral spheres
+        count = int(name[len("uneven"):] or 32)
+        out = media.uneven_batch(count=count, seed=0)
+        grids = [o["grid"] for o in out]
+        ks = [o["k"] for o in out]
+        med = [("chiral",) + media.sphere_chiral(o["grid"][0], radius=o["radius"], eps_in=o["eps_in"],
+                                                gamma_in=o["gamma_in"]) for o in out]
+        return grids, ks, med, 8
+    raise ValueError(name)
+
+
+def batch_leg(name, log=sys.stderr):
+    """Eigenpairs/s of one batched schedule against the plain per-instance loop."""
+    import torch
+
+    from paper_1402_6297_amd import nsf
+
+    grids, ks, med, nev = batch_instances(name)
+    kw = dict(res_tol=1e-8, cg_rtol=1e-10, seed=0)
+    # plain: one plan at a time
+    t0 = time.perf_counter()
+    plain_pairs, plain_mv = 0, 0
+    for i, (g, k, m) in enumerate(zip(grids, ks, med)):
+        with nsf.Plan(g, k) as P:
+            if m[0] == "chiral":
+                P.set_chiral(m[1], m[2])
+            else:
+                P.set_pseudochiral(0, 1, m[1], m[2])
+            st, om, res, stats = P.eigs(nev, seed=kw["seed"] + 1000003 * i, res_tol=kw["res_tol"],
+                                        cg_rtol=kw["cg_rtol"])
+            plain_pairs += stats["converged"]
+            plain_mv += stats["matvecs"]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print(f"[bench] {name} plain: {len(grids)} instances, {t_plain:.1f} s", file=log, flush=True)
+    with nsf.Batch(grids, ks) as B:
+        for i, m in enumerate(med):
+            if m[0] == "chiral":
+                B.set_chiral(i, m[1], m[2])
+            else:
+                B.set_pseudochiral(i, 0, 1, m[1], m[2])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, om, res, stats, wave = B.eigs(nev, **kw)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+    pairs = sum(s["converged"] for s in stats)
+    print(f"[bench] {name} batched: {t_batch:.1f} s, wave {wave}", file=log, flush=True)
+    return {"workload": name, "instances": len(grids), "nev": nev, "wave": wave,
+            "eigenpairs_per_s_batched": round(pairs / t_batch, 4),
+            "eigenpairs_per_s_plain": round(plain_pairs / t_plain, 4),
+            "s_batched": round(t_batch, 3), "s_plain": round(t_plain, 3),
+            "max_residual": float(res.max()), "status": st,
+            "grids": sorted(set(f"{g[0]}^3" for g in grids))}
+
+
 def cpu_baseline(w, eps, gam, budget_s=20.0):
     """The oracle's matrix-free A_r apply on the host, bounded to ~budget_s."""
     from oracle import medium, nfgep
@@ -150,6 +214,8 @@ def main():
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="only run this many A_r applies plus a 1 GiB device copy (for rocprofv3)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a rocprofv3 kernel-stats table and exit")
+    ap.add_argument("--batch", default="uneven6",
+                    help="batched-vs-plain leg after the steps: kpath128, uneven32, unevenN, or none")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ar_apply_traffic_<workload>.json from two --pmc runs and exit")
     args = ap.parse_args()
@@ -272,6 +338,8 @@ def main():
                  "lanczos_steps": stats["lanczos_steps"], "restarts": stats["restarts"],
                  "s_per_solve": round(elapsed / args.steps, 3)},
     }
+    if args.batch != "none":
+        line["batch"] = batch_leg(args.batch)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, eps, gam)

@@ -40,11 +40,11 @@ struct Split {
 // ------------------------------------------------------------ y / z passes
 // P pencils (consecutive x) per workgroup, N2 threads per pencil, lane order
 // p fastest.  LDS tile[(e) * P + p], e = n2 + N2 k1.
-template <int N1, int N2, int S>
+template <int N1, int N2, int S, bool BT = false>
 __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2* __restrict__ fld,
                                              int P, int post_twist, int pre_twist, const int* skip,
                                              const InstDesc* __restrict__ insts) {
-  if (insts) {
+  if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
     fld = d.fld;
@@ -106,11 +106,11 @@ __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2
 }
 
 // ------------------------------------------------------ z pass with medium
-template <int N1, int N2>
+template <int N1, int N2, bool BT = false>
 __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med,
                                                 double2* __restrict__ fld, int P, const int* skip,
                                                 const InstDesc* __restrict__ insts) {
-  if (insts) {
+  if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
     med = d.med;
@@ -207,12 +207,12 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
 
 // ------------------------------------------------------------- x passes
 // R rows per workgroup; LDS tile[(c * R + r) * (N + 1) + e].
-template <int N1, int N2, int PART, bool CG = false>
+template <int N1, int N2, int PART, bool CG = false, bool BT = false>
 __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const double2* __restrict__ y,
                                                       double2* __restrict__ fld, int R,
                                                       const int* skip, CgFuse cg,
                                                       const InstDesc* __restrict__ insts) {
-  if (insts) {
+  if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
     y = d.vin;
@@ -325,12 +325,12 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   }
 }
 
-template <int N1, int N2, int PART, bool CG = false>
+template <int N1, int N2, int PART, bool CG = false, bool BT = false>
 __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
                                                      double2* __restrict__ out, int R,
                                                      const int* skip, CgFuse cg,
                                                      const InstDesc* __restrict__ insts) {
-  if (insts) {
+  if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
     fld = d.fld;
@@ -517,7 +517,13 @@ hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int
   const dim3 block(P * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + N * P);
 #define L_YZ(A, B)                                                                                   \
-  if (dir > 0)                                                                                       \
+  if (insts && dir > 0)                                                                              \
+    hipLaunchKernelGGL((k_fyz<A, B, +1, true>), grid, block, lds, s, g, t, axis, fld, P, post_twist, \
+                       pre_twist, skip, insts);                                                      \
+  else if (insts)                                                                                    \
+    hipLaunchKernelGGL((k_fyz<A, B, -1, true>), grid, block, lds, s, g, t, axis, fld, P, post_twist, \
+                       pre_twist, skip, insts);                                                      \
+  else if (dir > 0)                                                                                  \
     hipLaunchKernelGGL((k_fyz<A, B, +1>), grid, block, lds, s, g, t, axis, fld, P, post_twist,       \
                        pre_twist, skip, insts);                                                      \
   else                                                                                               \
@@ -543,11 +549,17 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
   // Workgroups above 64 KiB of LDS opt in once per kernel.
 #define L_MID(A, B)                                                                                 \
   if (lds > 65536) {                                                                                \
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_mid<A, B>),       \
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_mid<A, B>),             \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
+    if (e == hipSuccess)                                                                            \
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_mid<A, B, true>),                \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
     if (e != hipSuccess) return e;                                                                  \
   }                                                                                                 \
-  hipLaunchKernelGGL((k_fz_mid<A, B>), grid, block, lds, s, g, t, med, fld, P, skip, insts);
+  if (insts)                                                                                        \
+    hipLaunchKernelGGL((k_fz_mid<A, B, true>), grid, block, lds, s, g, t, med, fld, P, skip, insts); \
+  else                                                                                              \
+    hipLaunchKernelGGL((k_fz_mid<A, B>), grid, block, lds, s, g, t, med, fld, P, skip, insts);
   NSF_FAST_SWITCH(N, L_MID)
 #undef L_MID
   return hipGetLastError();
@@ -566,9 +578,13 @@ hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, con
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+  if (insts && part != kPartBoth) return hipErrorInvalidValue;  // batched form covers both halves only
   const CgFuse none{};
 #define L_XI(A, B)                                                                                    \
-  if (part == kPartBoth)                                                                              \
+  if (part == kPartBoth && insts)                                                                     \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, false, true>), grid, block, lds, s, g, t, y,    \
+                       fld, R, skip, none, insts);                                                    \
+  else if (part == kPartBoth)                                                                         \
     hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth>), grid, block, lds, s, g, t, y, fld, R, skip,  \
                        none, insts);                                                                  \
   else if (part == kPartP)                                                                            \
@@ -595,9 +611,13 @@ hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, cons
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+  if (insts && part != kPartBoth) return hipErrorInvalidValue;  // batched form covers both halves only
   const CgFuse none{};
 #define L_XF(A, B)                                                                                     \
-  if (part == kPartBoth)                                                                               \
+  if (part == kPartBoth && insts)                                                                      \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, false, true>), grid, block, lds, s, g, t, fld,    \
+                       out, R, skip, none, insts);                                                     \
+  else if (part == kPartBoth)                                                                          \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth>), grid, block, lds, s, g, t, fld, out, R, skip,  \
                        none, insts);                                                                   \
   else if (part == kPartP)                                                                             \
@@ -636,8 +656,12 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
   const dim3 block(6 * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
 #define L_CGI(A, B)                                                                                  \
-  hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true>), grid, block, lds, s, g, t,             \
-                     (const double2*)nullptr, fld, R, skip, cg, insts);
+  if (insts)                                                                                         \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true, true>), grid, block, lds, s, g, t,     \
+                       (const double2*)nullptr, fld, R, skip, cg, insts);                            \
+  else                                                                                               \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true>), grid, block, lds, s, g, t,           \
+                       (const double2*)nullptr, fld, R, skip, cg, insts);
   NSF_FAST_SWITCH(N, L_CGI)
 #undef L_CGI
   return hipGetLastError();
@@ -658,8 +682,12 @@ hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg,
   const dim3 block(6 * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
 #define L_CGL(A, B)                                                                                  \
-  hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true>), grid, block, lds, s, g, t, fld, cg.q,   \
-                     R, skip, cg, insts);
+  if (insts)                                                                                         \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, true>), grid, block, lds, s, g, t, fld,  \
+                       cg.q, R, skip, cg, insts);                                                    \
+  else                                                                                               \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true>), grid, block, lds, s, g, t, fld, cg.q, \
+                       R, skip, cg, insts);
   NSF_FAST_SWITCH(N, L_CGL)
 #undef L_CGL
   return hipGetLastError();

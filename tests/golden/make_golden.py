@@ -5,7 +5,7 @@ the HIP library.  Inputs come from the seeded generators in
 ``paper_1402_6297_amd.media``.  Usage:
 
     python tests/golden/make_golden.py config1_16      # ~2 min
-    python tests/golden/make_golden.py config2_64      # ~1 h (ARPACK + CG in numpy)
+    python tests/golden/make_golden.py config2_64      # ~80 min (ARPACK + CG in numpy)
 
 Each entry records the workload, the oracle route and its tolerances.
 """

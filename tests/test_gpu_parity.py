@@ -273,6 +273,22 @@ def test_eigs_config1_golden():
     assert np.abs(om - ref).max() <= 1e-10 * ref.max()
 
 
+def test_eigs_config2_golden_64():
+    """64^3 chiral sphere at k=(0.25,0,0): the ten smallest omega against the stored
+    oracle values (ARPACK on the pencil with CG inner solves, residuals below 1e-12)."""
+    g = json.load(open(os.path.join(HERE, "golden", "config2_64.json")))
+    grid, k = tuple(g["grid"]), tuple(g["k"])
+    eps, gam = media.sphere_chiral(64)
+    ref = np.array(g["omega"])
+    assert max(g["residual"]) < 1e-11
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st, om, res, stats = P.eigs(10, res_tol=1e-9, cg_rtol=1e-11, seed=1)
+    assert st == nsf.NSF_OK
+    assert res.max() <= 1e-9
+    assert np.abs(om - ref).max() <= 1e-10 * ref.max()
+
+
 def test_eigs_homogeneous_closed_form_16():
     grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
     eps0, g0 = 13.0, 0.5
