@@ -112,6 +112,74 @@ def batch_leg(name, log=sys.stderr):
             "grids": sorted(set(f"{g[0]}^3" for g in grids))}
 
 
+def grad_leg(nvox, log=sys.stderr, h=1e-6, nev=4):
+    """Gradient of S = sum of the 4 smallest omega on the 64^3 noise medium
+    (Gaussian-filtered eps in [1, 13], gamma = 0.3 (eps - 1) / 12, k = (0.1, 0.1, 0.1)):
+    cost of the gradient kernel against the eigensolve, and central differences
+    (step h, every perturbed solve in one batch) at nvox seeded voxels."""
+    import torch
+
+    from paper_1402_6297_amd import media, nsf
+
+    grid, k = (64, 64, 64), (0.1, 0.1, 0.1)
+    eps, gam = media.noise_chiral(64, sigma_vox=2.0, seed=0)
+    n = eps.size
+    kw = dict(res_tol=1e-11, cg_rtol=1e-12)
+    vox = np.random.default_rng(1).choice(n, size=nvox, replace=False)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        Y = torch.empty(nev * 4 * n, dtype=torch.complex128, device="cuda")
+        P.eigs(nev, Y=Y, **kw)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, om, res, stats = P.eigs(nev, Y=Y, **kw)
+        torch.cuda.synchronize()
+        t_eigs = time.perf_counter() - t0
+        de = torch.empty(n, dtype=torch.float64, device="cuda")
+        dg = torch.empty_like(de)
+        P.eig_grad(om, Y, np.ones(nev), de, dg)
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.eig_grad(om, Y, np.ones(nev), de, dg)
+        e1.record()
+        torch.cuda.synchronize()
+        t_grad = e0.elapsed_time(e1) / reps * 1e-3
+        an = np.stack([de.cpu().numpy()[vox], dg.cpu().numpy()[vox]])
+    print(f"[bench] grad64: eigensolve {t_eigs:.3f} s, gradient {t_grad * 1e6:.0f} us", file=log, flush=True)
+    fields = []
+    for which in range(2):
+        for v in vox:
+            for s in (+1, -1):
+                e, g = eps.copy().ravel(), gam.copy().ravel()
+                (e if which == 0 else g)[v] += s * h
+                fields.append((e.reshape(eps.shape), g.reshape(eps.shape)))
+    t0 = time.perf_counter()
+    with nsf.Batch([grid] * len(fields), [k] * len(fields)) as B:
+        for i, (e, g) in enumerate(fields):
+            B.set_chiral(i, e, g)
+        stb, omb, resb, _, wave = B.eigs(nev, **kw)
+    t_fd = time.perf_counter() - t0
+    S = omb.sum(axis=1).reshape(2, nvox, 2)
+    fd = (S[:, :, 0] - S[:, :, 1]) / (2 * h)
+    err = np.abs(an - fd)
+    relerr = err / np.abs(an)
+    scale = np.abs(an).max(axis=1, keepdims=True)
+    ok = (err <= 5e-3 * np.abs(an)) | (err <= 1e-3 * scale)
+    print(f"[bench] grad64: {2 * nvox} FD pairs in {t_fd:.1f} s (wave {wave}), pass {int(ok.sum())}/{ok.size}",
+          file=log, flush=True)
+    return {"workload": "grad64: 64^3 Gaussian-filtered noise eps in [1,13], gamma=0.3(eps-1)/12, "
+                        "k=(0.1,0.1,0.1), S = sum of 4 smallest omega",
+            "omega": [round(x, 12) for x in om.tolist()], "eigs_status": st,
+            "s_eigensolve": round(t_eigs, 4), "s_gradient": round(t_grad, 6),
+            "gradient_over_eigensolve": round(t_grad / t_eigs, 6),
+            "fd_voxels": int(nvox), "fd_h": h, "fd_status": stb, "fd_pass": int(ok.sum()), "fd_total": int(ok.size),
+            "fd_max_rel_err_eps": float(relerr[0].max()), "fd_max_rel_err_gamma": float(relerr[1].max()),
+            "fd_median_rel_err": float(np.median(relerr)), "max_abs_grad_eps": float(scale[0, 0]),
+            "max_abs_grad_gamma": float(scale[1, 0]), "s_fd_batch": round(t_fd, 2)}
+
+
 def cpu_baseline(w, eps, gam, budget_s=20.0):
     """The oracle's matrix-free A_r apply on the host, bounded to ~budget_s."""
     from oracle import medium, nfgep
@@ -216,6 +284,8 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a rocprofv3 kernel-stats table and exit")
     ap.add_argument("--batch", default="uneven6",
                     help="batched-vs-plain leg after the steps: kpath128, uneven32, unevenN, or none")
+    ap.add_argument("--grad", type=int, default=0, metavar="NVOX",
+                    help="gradient leg at 64^3: kernel cost and central differences at NVOX voxels")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ar_apply_traffic_<workload>.json from two --pmc runs and exit")
     args = ap.parse_args()
@@ -340,6 +410,8 @@ def main():
     }
     if args.batch != "none":
         line["batch"] = batch_leg(args.batch)
+    if args.grad:
+        line["grad"] = grad_leg(args.grad)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, eps, gam)

@@ -457,6 +457,60 @@ int make_run(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
   return NSF_OK;
 }
 
+// Final values of the wanted pairs from exact operator applications: for each
+// Ritz vector v, A_r v by one apply (replacing the image carried along by the
+// CG recurrences), v rescaled to unit A_r-norm, theta = v^* B_r v / v^* A_r v,
+// and eta from B_r v - theta A_r v.  The Lanczos values differ from these only
+// by the rounding the recurrences accumulate (about 1e-14 relative), but the
+// reported omega and residual are then those of the returned vectors exactly.
+// Pairs are re-sorted by theta if the refinement swapped neighbours.
+int refine_run(Run* r) {
+  nsf_plan p = r->p;
+  hipStream_t s = p->stream;
+  const long long L = r->len;
+  for (int i = 0; i < r->nev; ++i) {
+    double2* v = r->V + (size_t)i * L;
+    double2* av = r->AV + (size_t)i * L;
+    int rc = apply_Ar_dev(p, v, av, nullptr);
+    if (rc) return rc;
+    r->st.matvecs += 1;
+    NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, v, r->bv, nullptr, s));
+    if ((rc = dot_async(p, v, av, L, 8))) return rc;
+    if ((rc = dot_async(p, v, r->bv, L, 9))) return rc;
+    NSF_HIP(p, hipStreamSynchronize(s));
+    const double a = p->h_res[8].x, b = p->h_res[9].x;
+    if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b))
+      return set_error(p, NSF_E_BREAKDOWN, "A_r-norm of a Ritz vector is not positive");
+    const double sc = 1.0 / std::sqrt(a);
+    NSF_HIP(p, launch_scale_copy(v, v, sc, 0.0, L, s));
+    NSF_HIP(p, launch_scale_copy(av, av, sc, 0.0, L, s));
+    r->theta[i] = b / a;
+    NSF_HIP(p, launch_residual_norms(p->geom, p->tabs, v, av, r->theta[i], p->d_partial,
+                                     reinterpret_cast<double*>(p->d_res + 64 + i), s));
+  }
+  NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_res + 64, sizeof(double2) * r->nev, hipMemcpyDeviceToHost, s));
+  NSF_HIP(p, hipStreamSynchronize(s));
+  bool all = true;
+  for (int i = 0; i < r->nev; ++i) {
+    const double2 r2 = p->h_res[64 + i];
+    r->eta[i] = std::sqrt(r2.x) / (std::fabs(r->theta[i]) * std::sqrt(r2.y));
+    if (!(r->theta[i] > 0.0) || !(r->eta[i] <= r->res_tol)) all = false;
+  }
+  r->converged = all;
+  // insertion sort by descending theta; columns move through the bv scratch
+  for (int i = 1; i < r->nev; ++i)
+    for (int j = i; j > 0 && r->theta[j] > r->theta[j - 1]; --j) {
+      double2* a0 = r->V + (size_t)(j - 1) * L;
+      double2* a1 = r->V + (size_t)j * L;
+      NSF_HIP(p, hipMemcpyAsync(r->bv, a0, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
+      NSF_HIP(p, hipMemcpyAsync(a0, a1, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
+      NSF_HIP(p, hipMemcpyAsync(a1, r->bv, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
+      std::swap(r->theta[j], r->theta[j - 1]);
+      std::swap(r->eta[j], r->eta[j - 1]);
+    }
+  return NSF_OK;
+}
+
 void finish_run(Run& r, double* omega, double* resid, nsf_stats* stats, double ms) {
   int nconv = 0;
   for (int i = 0; i < r.nev; ++i) {
@@ -496,6 +550,7 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
   std::vector<Run*> runs{&r};
   rc = run_engine(runs, p->stream);
   if (rc) return rc;
+  if ((rc = refine_run(&r))) return rc;
   if (Y_dev)
     NSF_HIP(p, hipMemcpyAsync(Y_dev, r.V, sizeof(double2) * (size_t)nev * r.len, hipMemcpyDeviceToDevice, p->stream));
   NSF_HIP(p, hipStreamSynchronize(p->stream));
@@ -572,6 +627,10 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
     }
     const int rc = run_engine(ptrs, b->stream);
     if (rc) return set_error(nullptr, rc, std::string("batch: ") + ptrs[0]->p->last_error);
+    for (int i = w0; i < w1; ++i) {
+      const int rr = refine_run(&runs[i - w0]);
+      if (rr) return set_error(nullptr, rr, "instance " + std::to_string(i) + ": " + b->plans[i]->last_error);
+    }
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     for (int i = w0; i < w1; ++i) {
       Run& r = runs[i - w0];

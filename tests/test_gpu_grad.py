@@ -1,0 +1,132 @@
+"""Eigenvalue gradients on the GPU: the autograd path against the oracle's dense
+perturbation formula, the homogeneous closed form, and central finite differences
+of the GPU eigenvalues on the 64^3 noise medium (Gaussian-filtered eps in [1, 13],
+gamma = 0.3 (eps - 1) / 12, k = (0.1, 0.1, 0.1), S = sum of the 4 smallest omega).
+"""
+import numpy as np
+import pytest
+
+from oracle import grad, yee
+from paper_1402_6297_amd import media, nsf
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel(x, ref):
+    return np.abs(x - ref).max() / np.abs(ref).max()
+
+
+def test_autograd_matches_oracle_6():
+    from paper_1402_6297_amd import autograd
+
+    grid, k = (6, 6, 6), (0.1, 0.2, 0.3)
+    eps, gam = media.noise_chiral(6, sigma_vox=1.0, seed=7)
+    om_ref, de_ref, dg_ref = grad.chiral_eigs_and_grads(grid, k, eps, gam, 3)
+    e = dev(eps).requires_grad_(True)
+    g = dev(gam).requires_grad_(True)
+    om = autograd.eigenvalues(e, g, grid, k, 3, res_tol=1e-11, cg_rtol=1e-13)
+    w = torch.tensor([1.0, 0.5, -2.0], dtype=torch.float64, device="cuda")
+    (om * w).sum().backward()
+    assert rel(om.detach().cpu().numpy(), om_ref) < 1e-10
+    wn = w.cpu().numpy()
+    assert rel(e.grad.cpu().numpy().ravel(), (wn[:, None] * de_ref).sum(0)) < 1e-8
+    assert rel(g.grad.cpu().numpy().ravel(), (wn[:, None] * dg_ref).sum(0)) < 1e-8
+
+
+def _closed_form(grid, k, eps0, g0):
+    L1, L2, L3 = yee.lambdas(grid, k)
+    s2 = np.abs(L1) ** 2 + np.abs(L2) ** 2 + np.abs(L3) ** 2
+    c = L1 ** 2 + L2 ** 2 + L3 ** 2
+    Phi = eps0 - g0 ** 2
+    disc = np.sqrt(eps0 * (s2 - c.real) ** 2 + Phi * c.imag ** 2)
+    w2 = np.concatenate([eps0 * s2 - g0 ** 2 * c.real + g0 * disc, eps0 * s2 - g0 ** 2 * c.real - g0 * disc])
+    return np.sort(np.sqrt(w2[w2 > 0]) / Phi)
+
+
+def test_grad_sum_equals_homogeneous_derivative_16():
+    """In a homogeneous medium the per-voxel gradients summed over the grid are the
+    derivatives of the closed-form dispersion relation with respect to the constant
+    eps and gamma (differenced analytically-smooth formula, step 1e-5)."""
+    grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
+    eps0, g0, nev = 9.0, 0.4, 4
+    eps, gam = media.homogeneous(16, eps=eps0, gamma=g0)
+    cf = _closed_form(grid, k, eps0, g0)[:nev]
+    assert np.diff(cf).min() > 1e-6 * cf.max()  # simple eigenvalues
+    h = 1e-5
+    dcf_e = (_closed_form(grid, k, eps0 + h, g0)[:nev] - _closed_form(grid, k, eps0 - h, g0)[:nev]) / (2 * h)
+    dcf_g = (_closed_form(grid, k, eps0, g0 + h)[:nev] - _closed_form(grid, k, eps0, g0 - h)[:nev]) / (2 * h)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        Y = torch.empty(nev * 4 * P.n, dtype=torch.complex128, device="cuda")
+        st, om, res, _ = P.eigs(nev, res_tol=1e-11, cg_rtol=1e-12, Y=Y)
+        assert st == nsf.NSF_OK
+        assert rel(om, cf) < 1e-10
+        for j in range(nev):
+            w = np.zeros(nev)
+            w[j] = 1.0
+            de = torch.empty(P.n, dtype=torch.float64, device="cuda")
+            dg = torch.empty_like(de)
+            P.eig_grad(om, Y, w, de, dg)
+            torch.cuda.synchronize()
+            assert abs(de.sum().item() - dcf_e[j]) <= 1e-7 * abs(dcf_e[j])
+            assert abs(dg.sum().item() - dcf_g[j]) <= 1e-7 * max(abs(dcf_g[j]), 1e-3)
+
+
+def fd_check(nvox, seed_vox=1, h=1e-6, nev=4, res_tol=1e-11, cg_rtol=1e-12):
+    """Central differences of S = sum of the nev smallest omega at nvox voxels of the
+    64^3 noise medium, for eps and gamma, with every perturbed solve in one batch.
+    Returns (analytic, fd) arrays of shape (2, nvox) and the base omega."""
+    grid, k = (64, 64, 64), (0.1, 0.1, 0.1)
+    eps, gam = media.noise_chiral(64, sigma_vox=2.0, seed=0)
+    n = eps.size
+    vox = np.random.default_rng(seed_vox).choice(n, size=nvox, replace=False)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        Y = torch.empty(nev * 4 * n, dtype=torch.complex128, device="cuda")
+        st, om, res, _ = P.eigs(nev, res_tol=res_tol, cg_rtol=cg_rtol, Y=Y)
+        assert st == nsf.NSF_OK
+        de = torch.empty(n, dtype=torch.float64, device="cuda")
+        dg = torch.empty_like(de)
+        P.eig_grad(om, Y, np.ones(nev), de, dg)
+        torch.cuda.synchronize()
+        an = np.stack([de.cpu().numpy()[vox], dg.cpu().numpy()[vox]])
+    fields = []
+    for which in range(2):
+        for v in vox:
+            for s in (+1, -1):
+                e, g = eps.copy().ravel(), gam.copy().ravel()
+                (e if which == 0 else g)[v] += s * h
+                fields.append((e.reshape(eps.shape), g.reshape(eps.shape)))
+    with nsf.Batch([grid] * len(fields), [k] * len(fields)) as B:
+        for i, (e, g) in enumerate(fields):
+            B.set_chiral(i, e, g)
+        st, omb, resb, _, _ = B.eigs(nev, res_tol=res_tol, cg_rtol=cg_rtol)
+    assert st == nsf.NSF_OK
+    S = omb.sum(axis=1).reshape(2, nvox, 2)
+    fd = (S[:, :, 0] - S[:, :, 1]) / (2 * h)
+    return an, fd, om
+
+
+def fd_agrees(an, fd):
+    """Per voxel: relative error <= 5e-3, or absolute error <= 1e-3 max |dS| (the FD
+    difference of S is ~1e-11 against FP64 eigenvalue noise of ~1e-14)."""
+    err = np.abs(an - fd)
+    scale = np.abs(an).max(axis=1, keepdims=True)
+    return (err <= 5e-3 * np.abs(an)) | (err <= 1e-3 * scale)
+
+
+def test_grad_central_differences_64():
+    an, fd, om = fd_check(nvox=4)
+    ok = fd_agrees(an, fd)
+    assert ok.all(), (an, fd)
