@@ -99,11 +99,12 @@ def batch_leg(name, log=sys.stderr):
                 B.set_pseudochiral(i, 0, 1, m[1], m[2])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        shapes = B.autotune(reps=5)  # tiling per grid shape, inside the timed region
         st, om, res, stats, wave = B.eigs(nev, **kw)
         torch.cuda.synchronize()
         t_batch = time.perf_counter() - t0
     pairs = sum(s["converged"] for s in stats)
-    print(f"[bench] {name} batched: {t_batch:.1f} s, wave {wave}", file=log, flush=True)
+    print(f"[bench] {name} batched: {t_batch:.1f} s, wave {wave}, {shapes} shapes autotuned", file=log, flush=True)
     return {"workload": name, "instances": len(grids), "nev": nev, "wave": wave,
             "eigenpairs_per_s_batched": round(pairs / t_batch, 4),
             "eigenpairs_per_s_plain": round(plain_pairs / t_plain, 4),

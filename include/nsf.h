@@ -97,8 +97,15 @@ enum {
                             1: generic LDS-staged passes only,
                             2: single-wave passes (E'/H' lane halves) for the
                                x and fused z passes where possible          */
-  NSF_OPT_MID_COLS = 2   /* pencils per workgroup of the fused z pass: 1..16,
+  NSF_OPT_MID_COLS = 2,  /* pencils per workgroup of the fused z pass: 1..16,
                             power of two (default 8)                          */
+  NSF_OPT_CG_GRAPH = 3,  /* 1: the eigensolver captures one CG iteration of all
+                            unfinished instances as a HIP graph and replays it
+                            (default); 0: launches every kernel each iteration */
+  NSF_OPT_X_ROWS = 4,    /* grid rows per workgroup of the two-level x passes:
+                            1, 2 or 4 (default 4; lowered where it does not fit) */
+  NSF_OPT_YZ_COLS = 5    /* pencils per workgroup of the two-level y / z passes:
+                            1..16, power of two (default 16; lowered to fit)    */
 };
 
 /*
@@ -106,6 +113,26 @@ enum {
  * Host-only.  NSF_E_ARG for an unknown option or value.
  */
 int nsf_plan_set_option(nsf_plan plan, int option, int value);
+
+/*
+ * Autotuner of the FFT pass family and workgroup tiles.  Times reps A_r
+ * applies (after two untimed ones) under each candidate: the two-level
+ * register passes with NSF_OPT_MID_COLS in {4, 8, 16}, NSF_OPT_X_ROWS in
+ * {1, 2, 4} and NSF_OPT_YZ_COLS in {4, 8, 16}; the generic LDS-staged passes;
+ * the single-wave passes where the grid allows them.  Keeps the fastest as the
+ * plan's options.  Needs a medium (NSF_E_STATE); allocates two 4n scratch
+ * vectors for the call (NSF_E_NOMEM).  Results of later calls agree with the
+ * defaults to rounding.  Synchronises the stream.
+ *   reps    1..1000 timed applies per candidate
+ *   result  nullable; the chosen options, the average apply time with them and
+ *           with the defaults (microseconds), and the candidates timed
+ */
+typedef struct {
+  int fft_path, mid_cols, x_rows, yz_cols;
+  double us_best, us_default;
+  int tried;
+} nsf_tune;
+int nsf_plan_autotune(nsf_plan plan, int reps, nsf_tune* result);
 
 /* Free the plan and all device memory it owns.  NULL is accepted. */
 void nsf_plan_destroy(nsf_plan plan);
@@ -258,6 +285,12 @@ int nsf_batch_eigs(nsf_batch batch, int nev, double res_tol, double cg_rtol, int
                    int max_restarts, unsigned long long seed, double* omega_host,
                    double* resid_host, nsf_stats* stats, int* wave_size);
 void nsf_batch_destroy(nsf_batch batch);
+/*
+ * nsf_plan_autotune on the first instance of every distinct grid shape (its
+ * medium must be set), the chosen options copied to the other instances of
+ * that shape.  *shapes_tuned (nullable) receives the number of shapes.
+ */
+int nsf_batch_autotune(nsf_batch batch, int reps, int* shapes_tuned);
 
 /*
  * Dense Hermitian eigensolver on the host (cyclic complex Jacobi), the small

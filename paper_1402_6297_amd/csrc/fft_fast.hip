@@ -498,6 +498,15 @@ int pick_cols(int n1, int want) {
   return P;
 }
 
+// Rows per workgroup of an x pass over F fields: the plan's choice, halved
+// until the workgroup fits 384 lanes and 64 KB of LDS; 0 if one row does not.
+int x_rows_for(const Geom& g, const FastCfg& cfg, int F) {
+  const int N = g.n1;
+  int R = g.x_rows >= 4 ? 4 : (g.x_rows >= 2 ? 2 : 1);
+  while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
+  return F * R * cfg.N2 > 384 ? 0 : R;
+}
+
 }  // namespace
 
 bool fast_axis(int N) {
@@ -511,7 +520,7 @@ hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int
   const int N = axis == 1 ? g.n2 : g.n3;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
-  const int P = pick_cols(g.n1, 256 / cfg.N2 < 16 ? 256 / cfg.N2 : 16);
+  const int P = pick_cols(g.n1, std::min(std::min(256 / cfg.N2, 16), std::max(g.yz_cols, 1)));
   const long long other = (axis == 1) ? g.n3 : g.n2;
   const dim3 grid((unsigned)((g.n1 / P) * other), (unsigned)nf, (unsigned)ninst);
   const dim3 block(P * cfg.N2);
@@ -548,13 +557,14 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * N * P);
   // Workgroups above 64 KiB of LDS opt in once per kernel.
 #define L_MID(A, B)                                                                                 \
-  if (lds > 65536) {                                                                                \
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_mid<A, B>),             \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
-    if (e == hipSuccess)                                                                            \
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_mid<A, B, true>),                \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-    if (e != hipSuccess) return e;                                                                  \
+  if (lds > 65536) { /* opt in once per kernel, to the device limit (not a stream operation) */    \
+    static const hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_mid<A, B>), \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit()); \
+    static const hipError_t e1 = hipFuncSetAttribute(                                               \
+        reinterpret_cast<const void*>(&k_fz_mid<A, B, true>),                                       \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit());                              \
+    if (e0 != hipSuccess) return e0;                                                                \
+    if (e1 != hipSuccess) return e1;                                                                \
   }                                                                                                 \
   if (insts)                                                                                        \
     hipLaunchKernelGGL((k_fz_mid<A, B, true>), grid, block, lds, s, g, t, med, fld, P, skip, insts); \
@@ -571,9 +581,8 @@ hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, con
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
   const int F = part == kPartBoth ? 6 : 3;
-  int R = 4;
-  while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
-  if (F * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const int R = x_rows_for(g, cfg, F);
+  if (R == 0) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
@@ -604,9 +613,8 @@ hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, cons
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
   const int F = part == kPartBoth ? 6 : 3;
-  int R = 4;
-  while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
-  if (F * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const int R = x_rows_for(g, cfg, F);
+  if (R == 0) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
@@ -633,12 +641,9 @@ hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, cons
 
 // Rows per workgroup of the six-field x passes (0: no two-level pass).
 int fast_x_rows(const Geom& g) {
-  const int N = g.n1;
   FastCfg cfg;
-  if (!fast_cfg(N, cfg)) return 0;
-  int R = 4;
-  while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
-  return 6 * R * cfg.N2 > 384 ? 0 : R;
+  if (!fast_cfg(g.n1, cfg)) return 0;
+  return x_rows_for(g, cfg, 6);
 }
 
 hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg, double2* fld,
@@ -647,9 +652,8 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
-  int R = 4;
-  while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
-  if (6 * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const int R = x_rows_for(g, cfg, 6);
+  if (R == 0) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   *nparts = (int)grid.x;
@@ -673,9 +677,8 @@ hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg,
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
-  int R = 4;
-  while (R > 1 && (6 * R * cfg.N2 > 384 || (size_t)(N + 6 * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
-  if (6 * R * cfg.N2 > 384) return hipErrorInvalidValue;
+  const int R = x_rows_for(g, cfg, 6);
+  if (R == 0) return hipErrorInvalidValue;
   const long long rows = (long long)g.n2 * g.n3;
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   *nparts = (int)grid.x;

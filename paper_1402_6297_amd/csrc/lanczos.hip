@@ -117,45 +117,134 @@ int apply_all(std::vector<Group>& groups, hipStream_t s) {
   return NSF_OK;
 }
 
+// One CG iteration of every unfinished run, enqueued on each run's plan stream
+// (single instances) or on s (groups sharing launches).
+int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
+  for (Group& G : groups) {
+    const int na = (int)G.act.size();
+    if (na == 0) continue;
+    if (!G.fast) {
+      for (Run* r : G.act) {
+        const int rc = cg_iteration(r->p, r->w, cg_fusable(r->p));
+        if (rc) return rc;
+      }
+      continue;
+    }
+    nsf_plan p0 = G.act[0]->p;
+    const Geom& g = p0->geom;
+    const InstDesc* d = G.d_desc;
+    const CgFuse none{};
+    int np1 = 0, np5 = 0;
+    NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na));
+    NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na));
+    NSF_HIP(p0, launch_cgf_step(nullptr, np5, nullptr, s, d, na));
+  }
+  return NSF_OK;
+}
+
+// The CG iteration of the current set of unfinished runs as one HIP graph,
+// replayed between host reads of the CG states.  Every launch of an iteration
+// takes its scalars (alpha, beta, iteration count, done flag) from device
+// memory, so one captured iteration serves every iteration of every solve
+// until the set of unfinished runs changes.  Captured and replayed on a
+// private stream of default priority, ordered after the caller's stream by an
+// event; the graph holds kernel nodes only.
+struct CgGraph {
+  hipStream_t cs = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> sig;
+  int captures = 0;
+  ~CgGraph() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (ev) hipEventDestroy(ev);
+    if (cs) hipStreamDestroy(cs);
+  }
+};
+
+// Points the plans of the given runs at another stream for the guard's life.
+struct StreamSwap {
+  std::vector<std::pair<nsf_plan, hipStream_t>> saved;
+  StreamSwap(std::vector<Run*>& act, hipStream_t to) {
+    for (Run* r : act) {
+      saved.emplace_back(r->p, r->p->stream);
+      r->p->stream = to;
+    }
+  }
+  ~StreamSwap() {
+    for (auto& ps : saved) ps.first->stream = ps.second;
+  }
+};
+
+int cg_graph_ready(CgGraph& cg, std::vector<Group>& groups, std::vector<Run*>& act) {
+  nsf_plan p0 = act[0]->p;
+  std::vector<const void*> sig;
+  for (Group& G : groups) {
+    sig.push_back(reinterpret_cast<const void*>((size_t)G.act.size()));
+    for (Run* r : G.act) sig.push_back(r->p);
+  }
+  if (cg.exec && sig == cg.sig) return NSF_OK;
+  if (cg.exec) NSF_HIP(p0, hipGraphExecDestroy(cg.exec));
+  cg.exec = nullptr;
+  NSF_HIP(p0, hipStreamBeginCapture(cg.cs, hipStreamCaptureModeRelaxed));
+  const int rc = cg_iteration_all(groups, cg.cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(cg.cs, &graph);
+  if (rc) {
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+  }
+  NSF_HIP(p0, e);
+  const hipError_t ei = hipGraphInstantiate(&cg.exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  NSF_HIP(p0, ei);
+  cg.sig = sig;
+  cg.captures += 1;
+  return NSF_OK;
+}
+
 // w = A_r^{-1} bv by CG for every unfinished run, all advancing together.
-int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s) {
+int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, CgGraph* cgg) {
   for (Run* r : act) {
     nsf_plan p = r->p;
     NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, p->d_cg + r->len, r->len, p->d_partial, p->d_state,
                               r->cg_rtol, 5000, s));
+  }
+  bool graph = cgg != nullptr;
+  for (Run* r : act) graph = graph && r->p->opt_cg_graph;
+  hipStream_t ws = s;
+  if (graph) {
+    nsf_plan p0 = act[0]->p;
+    if (!cgg->cs) NSF_HIP(p0, hipStreamCreateWithFlags(&cgg->cs, hipStreamNonBlocking));
+    if (!cgg->ev) NSF_HIP(p0, hipEventCreateWithFlags(&cgg->ev, hipEventDisableTiming));
+    NSF_HIP(p0, hipEventRecord(cgg->ev, s));
+    NSF_HIP(p0, hipStreamWaitEvent(cgg->cs, cgg->ev, 0));
+    ws = cgg->cs;
+  }
+  StreamSwap swap(act, ws);
+  if (graph) {
+    const int rc = cg_graph_ready(*cgg, groups, act);
+    if (rc) return rc;
   }
   std::vector<double> rr_prev(act.size(), -1.0);
   std::vector<int> it_prev(act.size(), 0);
   int chunk = 4;
   for (;;) {
     for (int c = 0; c < chunk; ++c) {
-      for (Group& G : groups) {
-        const int na = (int)G.act.size();
-        if (na == 0) continue;
-        if (!G.fast) {
-          for (Run* r : G.act) {
-            const int rc = cg_iteration(r->p, r->w, cg_fusable(r->p));
-            if (rc) return rc;
-          }
-          continue;
-        }
-        nsf_plan p0 = G.act[0]->p;
-        const Geom& g = p0->geom;
-        const InstDesc* d = G.d_desc;
-        const CgFuse none{};
-        int np1 = 0, np5 = 0;
-        NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na));
-        NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
-        NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
-        NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na));
-        NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
-        NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na));
-        NSF_HIP(p0, launch_cgf_step(nullptr, np5, nullptr, s, d, na));
+      if (graph) {
+        NSF_HIP(act[0]->p, hipGraphLaunch(cgg->exec, ws));
+      } else {
+        const int rc = cg_iteration_all(groups, ws);
+        if (rc) return rc;
       }
     }
     for (Run* r : act)
-      NSF_HIP(r->p, hipMemcpyAsync(r->p->h_state, r->p->d_state, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    NSF_HIP(act[0]->p, hipStreamSynchronize(s));
+      NSF_HIP(r->p, hipMemcpyAsync(r->p->h_state, r->p->d_state, sizeof(CgState), hipMemcpyDeviceToHost, ws));
+    NSF_HIP(act[0]->p, hipStreamSynchronize(ws));
     bool all = true;
     int next = 1;
     for (size_t i = 0; i < act.size(); ++i) {
@@ -309,7 +398,8 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
   std::vector<Group> groups;
   for (Run* r : runs) {
     const Geom& g = r->p->geom;
-    auto k = std::make_tuple(g.n1, g.n2, g.n3, g.alpha, g.beta, r->p->opt_fft_path, r->p->opt_mid_cols);
+    auto k = std::make_tuple(g.n1, g.n2, g.n3, g.alpha, g.beta, r->p->opt_fft_path,
+                             r->p->opt_mid_cols * 1024 + g.x_rows * 32 + g.yz_cols);
     if (!key.count(k)) {
       key[k] = (int)groups.size();
       groups.emplace_back();
@@ -328,6 +418,7 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
       NSF_HIP(p0, hipHostMalloc(&G.h_desc, sizeof(InstDesc) * 2 * G.cap));
     }
   }
+  CgGraph cg_graph;
   auto release = [&]() {
     hipStreamSynchronize(s);
     for (Group& G : groups) {
@@ -364,7 +455,7 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
       if (!r->finished) act.push_back(r);
     if (act.empty()) break;
     // expand: w = A_r^{-1} B_r V[nb-1], z = A_r w
-    if ((rc = cg_all(groups, act, s))) return fail(rc);
+    if ((rc = cg_all(groups, act, s, &cg_graph))) return fail(rc);
     if ((rc = apply_all(groups, s))) return fail(rc);
     for (Run* r : act) {
       r->st.matvecs += 1;
@@ -586,6 +677,31 @@ void nsf_batch_destroy(nsf_batch b) {
   if (!b) return;
   for (nsf_plan p : b->plans) nsf_plan_destroy(p);
   delete b;
+}
+
+int nsf_batch_autotune(nsf_batch b, int reps, int* shapes_tuned) {
+  if (!b) return set_error(nullptr, NSF_E_ARG, "batch is NULL");
+  std::map<std::tuple<int, int, int>, nsf_plan> tuned;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    nsf_plan p = b->plans[i];
+    const Geom& g = p->geom;
+    const auto key = std::make_tuple(g.n1, g.n2, g.n3);
+    auto it = tuned.find(key);
+    if (it == tuned.end()) {
+      p->stream = b->stream;
+      const int rc = nsf_plan_autotune(p, reps, nullptr);
+      if (rc) return set_error(nullptr, rc, "instance " + std::to_string(i) + ": " + p->last_error);
+      tuned[key] = p;
+    } else {
+      const nsf_plan q = it->second;
+      p->opt_fft_path = q->opt_fft_path;
+      p->opt_mid_cols = q->opt_mid_cols;
+      p->geom.x_rows = q->geom.x_rows;
+      p->geom.yz_cols = q->geom.yz_cols;
+    }
+  }
+  if (shapes_tuned) *shapes_tuned = (int)tuned.size();
+  return NSF_OK;
 }
 
 int nsf_batch_plan(nsf_batch b, int i, nsf_plan* plan) {

@@ -53,6 +53,9 @@ struct Geom {
   int n1, n2, n3;
   long long n;
   double alpha, beta;
+  // launch tiling of the two-level passes (tuning only; results do not depend on it)
+  int x_rows = 4;    // rows per workgroup of the x passes (1, 2, 4; lowered to fit)
+  int yz_cols = 16;  // pencils per workgroup of the y / z passes (1..16, lowered to fit)
 };
 
 enum MediumKind { kMedNone = 0, kMedChiral = 1, kMedPseudo = 2 };
@@ -285,6 +288,7 @@ struct nsf_plan_s {
   // options (nsf_plan_set_option)
   int opt_fft_path = 0;     // 0 auto, 1 generic LDS-staged, 2 two-level without single-wave
   int opt_mid_cols = 8;     // pencils per workgroup of the fused z pass
+  int opt_cg_graph = 1;     // CG iterations of the eigensolver replayed from a HIP graph
 
   std::string last_error;
 };

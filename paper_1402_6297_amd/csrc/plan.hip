@@ -308,6 +308,19 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
       if (value < 1 || value > 16 || (value & (value - 1))) return set_error(p, NSF_E_ARG, "NSF_OPT_MID_COLS takes 1, 2, 4, 8 or 16");
       p->opt_mid_cols = value;
       return NSF_OK;
+    case NSF_OPT_X_ROWS:
+      if (value != 1 && value != 2 && value != 4) return set_error(p, NSF_E_ARG, "NSF_OPT_X_ROWS takes 1, 2 or 4");
+      p->geom.x_rows = value;
+      return NSF_OK;
+    case NSF_OPT_YZ_COLS:
+      if (value < 1 || value > 16 || (value & (value - 1)))
+        return set_error(p, NSF_E_ARG, "NSF_OPT_YZ_COLS takes 1, 2, 4, 8 or 16");
+      p->geom.yz_cols = value;
+      return NSF_OK;
+    case NSF_OPT_CG_GRAPH:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_GRAPH takes 0 or 1");
+      p->opt_cg_graph = value;
+      return NSF_OK;
     default:
       return set_error(p, NSF_E_ARG, "unknown option");
   }

@@ -1,0 +1,127 @@
+// Launch-tiling autotuner: times the A_r apply of a plan under each candidate
+// tiling of its FFT passes and keeps the fastest.  The candidates are the pass
+// families (two-level register passes, generic LDS-staged passes, single-wave
+// x and z passes) and, for the two-level family, the workgroup tiles: pencils
+// per workgroup of the fused z pass, rows per workgroup of the x passes and
+// pencils per workgroup of the y / z passes.  Every candidate computes the same
+// transforms; only the arithmetic order of the CG reductions (partials per
+// workgroup) can change, so results agree to rounding.
+#include <algorithm>
+#include <vector>
+
+#include "nsf_internal.h"
+
+namespace nsf {
+namespace {
+
+struct Tiling {
+  int path, mid, xr, yz;
+};
+
+void apply_tiling(nsf_plan p, const Tiling& t) {
+  p->opt_fft_path = t.path;
+  p->opt_mid_cols = t.mid;
+  p->geom.x_rows = t.xr;
+  p->geom.yz_cols = t.yz;
+}
+
+// Average milliseconds of one A_r apply (after two untimed ones).
+int time_apply(nsf_plan p, const double2* u, double2* out, int reps, hipEvent_t e0, hipEvent_t e1, double* ms) {
+  for (int i = 0; i < 2; ++i) {
+    const int rc = apply_Ar_dev(p, u, out, nullptr);
+    if (rc) return rc;
+  }
+  NSF_HIP(p, hipEventRecord(e0, p->stream));
+  for (int i = 0; i < reps; ++i) {
+    const int rc = apply_Ar_dev(p, u, out, nullptr);
+    if (rc) return rc;
+  }
+  NSF_HIP(p, hipEventRecord(e1, p->stream));
+  NSF_HIP(p, hipEventSynchronize(e1));
+  float f = 0;
+  NSF_HIP(p, hipEventElapsedTime(&f, e0, e1));
+  *ms = (double)f / reps;
+  return NSF_OK;
+}
+
+}  // namespace
+}  // namespace nsf
+
+using namespace nsf;
+
+extern "C" {
+
+int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  if (reps < 1 || reps > 1000) return set_error(p, NSF_E_ARG, "reps must be in 1..1000");
+  if (p->medium_kind == kMedNone) return set_error(p, NSF_E_STATE, "no medium set");
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  const Geom& g = p->geom;
+  const long long len = 4 * g.n;
+  const Tiling dflt{0, 8, 4, 16};
+  std::vector<Tiling> cand{dflt};
+  const bool fast = fast_axis(g.n1) || fast_axis(g.n2) || fast_axis(g.n3);
+  if (fast)
+    for (int mid : {4, 8, 16})
+      for (int xr : {1, 2, 4})
+        for (int yz : {4, 8, 16}) {
+          const Tiling t{0, mid, xr, yz};
+          if (!(t.mid == dflt.mid && t.xr == dflt.xr && t.yz == dflt.yz)) cand.push_back(t);
+        }
+  cand.push_back(Tiling{1, 8, 4, 16});
+  if (wave_axis(g.n1) || wave_mid_ok(g)) cand.push_back(Tiling{2, 8, 4, 16});
+
+  const Tiling saved{p->opt_fft_path, p->opt_mid_cols, g.x_rows, g.yz_cols};
+  double2* buf = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (buf) {
+      hipStreamSynchronize(p->stream);
+      hipFree(buf);
+    }
+  };
+  auto fail = [&](int code) {
+    apply_tiling(p, saved);
+    cleanup();
+    return code;
+  };
+  if (hipMalloc(&buf, sizeof(double2) * 2 * (size_t)len) != hipSuccess) {
+    buf = nullptr;
+    return set_error(p, NSF_E_NOMEM, "autotune: device allocation failed");
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(set_error(p, NSF_E_HIP, "autotune: event creation failed"));
+  if (launch_randn(buf, len, 0x5eedULL, p->stream) != hipSuccess)
+    return fail(set_error(p, NSF_E_HIP, "autotune: launch failed"));
+  double best_ms = 0, dflt_ms = 0;
+  Tiling best = dflt;
+  int tried = 0;
+  for (const Tiling& t : cand) {
+    apply_tiling(p, t);
+    double ms = 0;
+    if ((rc = time_apply(p, buf, buf + len, reps, e0, e1, &ms))) return fail(rc);
+    ++tried;
+    if (tried == 1) dflt_ms = ms;
+    if (tried == 1 || ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  apply_tiling(p, best);
+  cleanup();
+  if (result) {
+    result->fft_path = best.path;
+    result->mid_cols = best.mid;
+    result->x_rows = best.xr;
+    result->yz_cols = best.yz;
+    result->us_best = best_ms * 1e3;
+    result->us_default = dflt_ms * 1e3;
+    result->tried = tried;
+  }
+  return NSF_OK;
+}
+
+}  // extern "C"

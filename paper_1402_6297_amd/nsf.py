@@ -30,6 +30,9 @@ NSF_E_STATE = -8
 
 NSF_OPT_FFT_PATH = 1
 NSF_OPT_MID_COLS = 2
+NSF_OPT_CG_GRAPH = 3
+NSF_OPT_X_ROWS = 4
+NSF_OPT_YZ_COLS = 5
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",
@@ -38,6 +41,7 @@ EXPORTED = [
     "nsf_apply_Ar", "nsf_apply_Br", "nsf_profile_Ar", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
     "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
     "nsf_batch_create", "nsf_batch_plan", "nsf_batch_eigs", "nsf_batch_destroy",
+    "nsf_plan_autotune", "nsf_batch_autotune",
 ]
 
 
@@ -47,6 +51,14 @@ class nsf_stats(C.Structure):
                 ("converged", C.c_int), ("ortho_passes", C.c_int), ("cg_iters_avg", C.c_double),
                 ("ms_total", C.c_double),
                 ("bytes_alg", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class nsf_tune(C.Structure):
+    _fields_ = [("fft_path", C.c_int), ("mid_cols", C.c_int), ("x_rows", C.c_int), ("yz_cols", C.c_int),
+                ("us_best", C.c_double), ("us_default", C.c_double), ("tried", C.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -107,6 +119,8 @@ def lib():
         "nsf_batch_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, DP, C.POINTER(nsf_stats),
                                C.POINTER(I)]),
         "nsf_batch_destroy": (None, [P]),
+        "nsf_plan_autotune": (I, [P, I, C.POINTER(nsf_tune)]),
+        "nsf_batch_autotune": (I, [P, I, C.POINTER(I)]),
         "nsf_status_string": (C.c_char_p, [I]),
         "nsf_last_error": (C.c_char_p, [P]),
     }
@@ -310,6 +324,19 @@ def nsf_batch_eigs(batch, count, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, 
     return status, omega, resid, [x.as_dict() for x in st], wave.value
 
 
+def nsf_plan_autotune(plan, reps=10):
+    """Returns the chosen tiling and timings as a dict (see nsf_tune)."""
+    t = nsf_tune()
+    _check(lib().nsf_plan_autotune(plan, int(reps), C.byref(t)), plan)
+    return t.as_dict()
+
+
+def nsf_batch_autotune(batch, reps=10):
+    shapes = C.c_int()
+    _check(lib().nsf_batch_autotune(batch, int(reps), C.byref(shapes)))
+    return shapes.value
+
+
 def nsf_batch_destroy(batch):
     lib().nsf_batch_destroy(batch)
 
@@ -343,6 +370,9 @@ class Batch:
 
     def eigs(self, nev, **kw):
         return nsf_batch_eigs(self.handle, self.count, nev, **kw)
+
+    def autotune(self, reps=10):
+        return nsf_batch_autotune(self.handle, reps)
 
     def close(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
@@ -430,3 +460,6 @@ class Plan:
 
     def eig_grad(self, omega, Y, weights, d_eps, d_gamma):
         return nsf_eig_grad(self.handle, omega, Y, weights, d_eps, d_gamma)
+
+    def autotune(self, reps=10):
+        return nsf_plan_autotune(self.handle, reps)

@@ -96,3 +96,38 @@ def test_hermitian_eig_matches_lapack(m):
 def test_status_strings():
     assert nsf.nsf_status_string(0) == "ok"
     assert "CG" in nsf.nsf_status_string(nsf.NSF_E_BREAKDOWN)
+
+
+@pytest.mark.parametrize("option,good,bad", [
+    (nsf.NSF_OPT_FFT_PATH, [0, 1, 2], [-1, 3]),
+    (nsf.NSF_OPT_MID_COLS, [1, 2, 4, 8, 16], [0, 3, 32]),
+    (nsf.NSF_OPT_CG_GRAPH, [0, 1], [-1, 2]),
+    (nsf.NSF_OPT_X_ROWS, [1, 2, 4], [0, 3, 8]),
+    (nsf.NSF_OPT_YZ_COLS, [1, 2, 4, 8, 16], [0, 6, 32]),
+])
+def test_plan_options_validate(option, good, bad):
+    p = nsf.nsf_plan_create(8, 8, 8, 1.0, (0.1, 0.2, 0.3), stream=0)
+    try:
+        for v in good:
+            assert nsf.nsf_plan_set_option(p, option, v) == nsf.NSF_OK
+        for v in bad:
+            with pytest.raises(nsf.NsfError) as e:
+                nsf.nsf_plan_set_option(p, option, v)
+            assert e.value.status == nsf.NSF_E_ARG
+        with pytest.raises(nsf.NsfError):
+            nsf.nsf_plan_set_option(p, 99, 0)
+    finally:
+        nsf.nsf_plan_destroy(p)
+
+
+def test_autotune_needs_a_medium():
+    p = nsf.nsf_plan_create(8, 8, 8, 1.0, (0.1, 0.2, 0.3), stream=0)
+    try:
+        with pytest.raises(nsf.NsfError) as e:
+            nsf.nsf_plan_autotune(p, 3)
+        assert e.value.status == nsf.NSF_E_STATE
+        with pytest.raises(nsf.NsfError) as e:
+            nsf.nsf_plan_autotune(p, 0)
+        assert e.value.status == nsf.NSF_E_ARG
+    finally:
+        nsf.nsf_plan_destroy(p)

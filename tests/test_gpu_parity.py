@@ -387,3 +387,84 @@ def test_batch_rejects_bad_instance():
         nsf.Batch([(16, 16, 16), (16, 16, 16)], [(0.1, 0.2, 0.3), (0.0, 0.0, 0.0)])
     assert e.value.status == nsf.NSF_E_KPOINT
     assert "instance 1" in nsf.nsf_last_error(None)
+
+
+@pytest.mark.parametrize("batched", [False, True], ids=["single", "batch"])
+def test_cg_graph_replay_matches_eager(batched):
+    """Eigensolves whose CG iterations replay a captured HIP graph (interleaved with
+    eager Lanczos work and host synchronisations) reproduce the eager launches bit
+    for bit: same eigenvalues, residuals and iteration counts."""
+    out = []
+    for graph in (0, 1):
+        if not batched:
+            with nsf.Plan((16, 16, 16), (0.1, 0.2, 0.3)) as P:
+                P.set_chiral(*media.sphere_chiral(16))
+                P.set_option(nsf.NSF_OPT_CG_GRAPH, graph)
+                st, om, res, stats = P.eigs(6, res_tol=1e-9, cg_rtol=1e-11, seed=5)
+                out.append((st, om, res, stats["matvecs"], stats["cg_iters_total"]))
+        else:
+            grids = [(16, 16, 16), (16, 16, 16), (8, 8, 8)]
+            ks = [(0.1, 0.2, 0.3), (0.3, 0.1, 0.2), (0.2, 0.2, 0.1)]
+            with nsf.Batch(grids, ks) as B:
+                for i, g in enumerate(grids):
+                    B.set_chiral(i, *media.sphere_chiral(*g))
+                    nsf.nsf_plan_set_option(B.plan(i), nsf.NSF_OPT_CG_GRAPH, graph)
+                st, om, res, stats, _ = B.eigs(5, res_tol=1e-9, cg_rtol=1e-11, seed=5)
+                out.append((st, om, res, [s["matvecs"] for s in stats], [s["cg_iters_total"] for s in stats]))
+    (s0, om0, r0, mv0, it0), (s1, om1, r1, mv1, it1) = out
+    assert s0 == s1 == nsf.NSF_OK
+    assert np.array_equal(om0, om1) and np.array_equal(r0, r1)
+    assert mv0 == mv1 and it0 == it1
+
+
+TILINGS = [(4, 1, 1), (4, 2, 4), (8, 4, 8), (16, 1, 16), (2, 2, 2), (1, 4, 16)]
+
+
+@pytest.mark.parametrize("mid,xr,yz", TILINGS, ids=[f"mid{a}-x{b}-yz{c}" for a, b, c in TILINGS])
+@pytest.mark.parametrize("grid,k,kind", [((64, 16, 48), (0.3, 0.0, 0.2), "chiral"),
+                                         ((16, 32, 64), (0.1, 0.2, 0.3), "pseudo_xz"),
+                                         ((96, 16, 16), (0.1, 0.4, 0.3), "noise")])
+def test_Ar_every_tiling_matches_oracle(grid, k, kind, mid, xr, yz):
+    """Each workgroup tiling the autotuner may pick computes the same A_r."""
+    n = grid[0] * grid[1] * grid[2]
+    eps, gam, tens, pair = _medium(kind, grid)
+    u = media.random_vector(4 * n, 6)
+    with nsf.Plan(grid, k) as P:
+        P.set_option(nsf.NSF_OPT_MID_COLS, mid)
+        P.set_option(nsf.NSF_OPT_X_ROWS, xr)
+        P.set_option(nsf.NSF_OPT_YZ_COLS, yz)
+        _set(P, eps, gam, pair)
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        assert rel(host(out), nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+
+
+def test_autotune_picks_a_tiling_with_unchanged_results():
+    grid, k = (48, 32, 64), (0.1, 0.2, 0.3)
+    n = grid[0] * grid[1] * grid[2]
+    eps, gam = media.sphere_chiral(*grid)
+    tens = medium.tensors_chiral(eps, gam)
+    u = media.random_vector(4 * n, 8)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st0, om0, _, _ = P.eigs(4, res_tol=1e-10, cg_rtol=1e-12)
+        t = P.autotune(reps=3)
+        assert t["tried"] >= 3 and t["us_best"] <= t["us_default"] and t["us_best"] > 0
+        assert t["fft_path"] in (0, 1, 2) and t["x_rows"] in (1, 2, 4)
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        assert rel(host(out), nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+        st1, om1, res1, _ = P.eigs(4, res_tol=1e-10, cg_rtol=1e-12)
+    assert st0 == st1 == nsf.NSF_OK
+    assert np.abs(om1 - om0).max() <= 1e-11 * om0.max()
+
+
+def test_batch_autotune_one_per_shape():
+    grids = [(16, 16, 16), (32, 32, 32), (16, 16, 16)]
+    ks = [(0.1, 0.2, 0.3), (0.2, 0.1, 0.3), (0.3, 0.3, 0.1)]
+    with nsf.Batch(grids, ks) as B:
+        for i, g in enumerate(grids):
+            B.set_chiral(i, *media.sphere_chiral(*g))
+        assert B.autotune(reps=2) == 2
+        st, om, res, stats, _ = B.eigs(4, res_tol=1e-9, cg_rtol=1e-11)
+    assert st == nsf.NSF_OK and res.max() <= 1e-9
