@@ -280,6 +280,8 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--fft-path", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_FFT_PATH)")
     ap.add_argument("--mid-cols", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_MID_COLS)")
+    ap.add_argument("--mid-pairs", type=int, default=-1, help="nsf_plan_set_option(NSF_OPT_MID_PAIRS)")
+    ap.add_argument("--autotune", action="store_true", help="autotune the plan's pass tiling first")
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="only run this many A_r applies plus a 1 GiB device copy (for rocprofv3)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a rocprofv3 kernel-stats table and exit")
@@ -320,6 +322,8 @@ def main():
     P.set_option(nsf.NSF_OPT_FFT_PATH, args.fft_path)
     if args.mid_cols:
         P.set_option(nsf.NSF_OPT_MID_COLS, args.mid_cols)
+    if args.mid_pairs >= 0:
+        P.set_option(nsf.NSF_OPT_MID_PAIRS, args.mid_pairs)
     dev_info = nsf.nsf_device_info(0)
     print(f"[bench] device {dev_info}", file=sys.stderr, flush=True)
     if w["kind"] == "chiral":
@@ -327,6 +331,10 @@ def main():
     else:
         P.set_pseudochiral(0, 1, eps, gam)
 
+    tuned = None
+    if args.autotune:
+        tuned = P.autotune(reps=5)
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
     # ---- isolated A_r apply: per-kernel HIP-event times and the whole apply
     u = torch.from_numpy(media.random_vector(4 * n, 0)).to("cuda")
     out = torch.empty_like(u)
@@ -401,6 +409,7 @@ def main():
                      "kernel": "A_r apply (all kernels of one apply, 336 n B algorithmic)",
                      "kernel_us": [round(x * 1e3, 2) for x in pass_ms]},
         "device": dev_info,
+        "autotune": tuned,
         "matvec": {"us_per_apply": round(apply_ms * 1e3, 2), "GBps_alg": round(apply_gbps, 2),
                    "bytes_alg": b_alg},
         "eigs": {"status": st, "omega": [round(x, 12) for x in om.tolist()],

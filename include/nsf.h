@@ -104,8 +104,11 @@ enum {
                             (default); 0: launches every kernel each iteration */
   NSF_OPT_X_ROWS = 4,    /* grid rows per workgroup of the two-level x passes:
                             1, 2 or 4 (default 4; lowered where it does not fit) */
-  NSF_OPT_YZ_COLS = 5    /* pencils per workgroup of the two-level y / z passes:
+  NSF_OPT_YZ_COLS = 5,   /* pencils per workgroup of the two-level y / z passes:
                             1..16, power of two (default 16; lowered to fit)    */
+  NSF_OPT_MID_PAIRS = 6  /* fused z pass of the two-level path: 1 one coupled
+                            (E', H') field pair per workgroup (default), 0 all
+                            six fields per workgroup                           */
 };
 
 /*
@@ -117,8 +120,9 @@ int nsf_plan_set_option(nsf_plan plan, int option, int value);
 /*
  * Autotuner of the FFT pass family and workgroup tiles.  Times reps A_r
  * applies (after two untimed ones) under each candidate: the two-level
- * register passes with NSF_OPT_MID_COLS in {4, 8, 16}, NSF_OPT_X_ROWS in
- * {1, 2, 4} and NSF_OPT_YZ_COLS in {4, 8, 16}; the generic LDS-staged passes;
+ * register passes with NSF_OPT_MID_PAIRS in {1, 0}, NSF_OPT_MID_COLS in
+ * {4, 8, 16}, NSF_OPT_X_ROWS in {1, 2, 4} and NSF_OPT_YZ_COLS in {4, 8, 16};
+ * the generic LDS-staged passes;
  * the single-wave passes where the grid allows them.  Keeps the fastest as the
  * plan's options.  Needs a medium (NSF_E_STATE); allocates two 4n scratch
  * vectors for the call (NSF_E_NOMEM).  Results of later calls agree with the
@@ -128,7 +132,7 @@ int nsf_plan_set_option(nsf_plan plan, int option, int value);
  *           with the defaults (microseconds), and the candidates timed
  */
 typedef struct {
-  int fft_path, mid_cols, x_rows, yz_cols;
+  int fft_path, mid_cols, x_rows, yz_cols, mid_pairs;
   double us_best, us_default;
   int tried;
 } nsf_tune;

@@ -205,6 +205,135 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
   }
 }
 
+// ------------------------------------------- z pass with medium, field pairs
+// The constitutive step couples the six fields only in pairs: chiral media pair
+// E'_c with H'_c; pseudochiral media with coupled axes (a, b) pair E'_a with
+// H'_b and E'_b with H'_a, and leave E'_o, H'_o (o the third axis) uncoupled.
+// In every pair the step is e' = (eps e - i g h) s, h' = (i g e + h) s with
+// s = 1/(n (eps - g^2)), where g = gamma for a coupled pair and g = 0 for the
+// uncoupled one.  One workgroup transforms one pair of P z-pencil columns, so
+// its LDS tile is a third of the six-field tile.  The three pairs of a tile
+// are dispatched to the same XCD one after another (when the tile count is a
+// multiple of 8), so the medium they all read is served from that XCD's L2.
+template <int N1, int N2, bool BT = false>
+__global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView med,
+                                                 double2* __restrict__ fld, int P, const int* skip,
+                                                 const InstDesc* __restrict__ insts) {
+  if constexpr (BT) {
+    const InstDesc& d = insts[blockIdx.z];
+    t = d.t;
+    med = d.med;
+    fld = d.fld;
+    skip = d.skip;
+  }
+  if (skip && *skip) return;
+  constexpr int N = N1 * N2;
+  constexpr int D = Split<N1, N2>::D;
+  extern __shared__ double2 sm[];
+  double2* twl = sm;
+  double2* tile = sm + N;  // [(h * N + e) * P + p], h = 0 (E field), 1 (H field)
+  const int twoff = g.n1 + g.n2;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = t.tw[twoff + i];
+  const int groups1 = g.n1 / P;
+  const unsigned tiles = (unsigned)groups1 * (unsigned)g.n2;
+  unsigned tix, q;
+  if ((tiles & 7u) == 0) {
+    const unsigned sq = blockIdx.x >> 3;
+    q = sq % 3u;
+    tix = (blockIdx.x & 7u) + 8u * (sq / 3u);
+  } else {
+    q = blockIdx.x % 3u;
+    tix = blockIdx.x / 3u;
+  }
+  int fe, fh;
+  bool coupled = true;
+  if (med.kind == kMedChiral) {
+    fe = (int)q;
+    fh = 3 + (int)q;
+  } else if (q == 0) {
+    fe = med.pa;
+    fh = 3 + med.pb;
+  } else if (q == 1) {
+    fe = med.pb;
+    fh = 3 + med.pa;
+  } else {
+    fe = med.po;
+    fh = 3 + med.po;
+    coupled = false;
+  }
+  const int p = threadIdx.x % P;
+  const int n2 = (threadIdx.x / P) % N2;
+  const int h = threadIdx.x / (P * N2);
+  const int i1_0 = (int)(tix % (unsigned)groups1) * P;
+  const int i2 = (int)(tix / (unsigned)groups1);
+  const long long base = (long long)i2 * g.n1 + i1_0;
+  const long long stride = (long long)g.n1 * g.n2;
+  const long long n = g.n;
+  double2* F = fld + (h == 0 ? fe : fh) * n + base + p;
+  double2* T = tile + h * N * P + p;
+  double2 v[N1];
+#pragma unroll
+  for (int n1 = 0; n1 < N1; ++n1) v[n1] = F[(n2 + N2 * n1) * stride];
+  __syncthreads();
+  // inverse z
+  step1<N1, N2, +1>(v, n2, twl);
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) T[(n2 + N2 * k1) * P] = v[k1];
+  __syncthreads();
+  double2 out[D][N2];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+#pragma unroll
+      for (int m = 0; m < N2; ++m) out[d][m] = T[(m + N2 * k1) * P];
+      reg_dft<N2, +1>(out[d]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) T[(k1 + N1 * k2) * P] = out[d][k2];
+    }
+  }
+  __syncthreads();
+  // constitutive step of the pair (times 1/n)
+  const double inv_n = 1.0 / (double)n;
+  for (int vx = threadIdx.x; vx < P * N; vx += blockDim.x) {
+    const int pp = vx % P, j = vx / P;
+    const double2 eg = med.eg[base + j * stride + pp];
+    const double eps = eg.x, gm = coupled ? eg.y : 0.0;
+    const double sc = inv_n / (eps - gm * gm);
+    const double2 e = tile[j * P + pp], hh = tile[(N + j) * P + pp];
+    tile[j * P + pp] = cscale(csub(cscale(e, eps), cmuli(cscale(hh, gm))), sc);
+    tile[(N + j) * P + pp] = cscale(cadd(cmuli(cscale(e, gm)), hh), sc);
+  }
+  __syncthreads();
+  // forward z
+#pragma unroll
+  for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[(n2 + N2 * n1) * P];
+  __syncthreads();
+  step1<N1, N2, -1>(v, n2, twl);
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) T[(n2 + N2 * k1) * P] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+      double2 u[N2];
+#pragma unroll
+      for (int m = 0; m < N2; ++m) u[m] = T[(m + N2 * k1) * P];
+      reg_dft<N2, -1>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) F[(k1 + N1 * k2) * stride] = u[k2];
+    }
+  }
+}
+
 // ------------------------------------------------------------- x passes
 // R rows per workgroup; LDS tile[(c * R + r) * (N + 1) + e].
 template <int N1, int N2, int PART, bool CG = false, bool BT = false>
@@ -549,6 +678,31 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
   const int N = g.n3;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
+  if (g.mid_pairs) {
+    int P = pick_cols(g.n1, P_want);
+    while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lds_limit())) P /= 2;
+    if (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lds_limit()) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(3 * (g.n1 / P) * g.n2), 1, (unsigned)ninst);
+    const dim3 block(2 * P * cfg.N2);
+    const size_t lds = sizeof(double2) * (size_t)(N + 2 * N * P);
+#define L_PAIR(A, B)                                                                                 \
+  if (lds > 65536) { /* opt in once per kernel, to the device limit (not a stream operation) */     \
+    static const hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_pair<A, B>), \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit());  \
+    static const hipError_t e1 = hipFuncSetAttribute(                                                \
+        reinterpret_cast<const void*>(&k_fz_pair<A, B, true>),                                       \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit());                               \
+    if (e0 != hipSuccess) return e0;                                                                 \
+    if (e1 != hipSuccess) return e1;                                                                 \
+  }                                                                                                  \
+  if (insts)                                                                                         \
+    hipLaunchKernelGGL((k_fz_pair<A, B, true>), grid, block, lds, s, g, t, med, fld, P, skip, insts); \
+  else                                                                                               \
+    hipLaunchKernelGGL((k_fz_pair<A, B>), grid, block, lds, s, g, t, med, fld, P, skip, insts);
+    NSF_FAST_SWITCH(N, L_PAIR)
+#undef L_PAIR
+    return hipGetLastError();
+  }
   int P = pick_cols(g.n1, P_want);
   while (P > 1 && (6 * P * cfg.N2 > 384 || (size_t)(N + 6 * N * P) * 16 > lds_limit())) P /= 2;
   if (6 * P * cfg.N2 > 384) return hipErrorInvalidValue;

@@ -399,7 +399,7 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
   for (Run* r : runs) {
     const Geom& g = r->p->geom;
     auto k = std::make_tuple(g.n1, g.n2, g.n3, g.alpha, g.beta, r->p->opt_fft_path,
-                             r->p->opt_mid_cols * 1024 + g.x_rows * 32 + g.yz_cols);
+                             r->p->opt_mid_cols * 2048 + g.mid_pairs * 1024 + g.x_rows * 32 + g.yz_cols);
     if (!key.count(k)) {
       key[k] = (int)groups.size();
       groups.emplace_back();
@@ -698,6 +698,7 @@ int nsf_batch_autotune(nsf_batch b, int reps, int* shapes_tuned) {
       p->opt_mid_cols = q->opt_mid_cols;
       p->geom.x_rows = q->geom.x_rows;
       p->geom.yz_cols = q->geom.yz_cols;
+      p->geom.mid_pairs = q->geom.mid_pairs;
     }
   }
   if (shapes_tuned) *shapes_tuned = (int)tuned.size();

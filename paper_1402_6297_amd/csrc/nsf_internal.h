@@ -56,6 +56,7 @@ struct Geom {
   // launch tiling of the two-level passes (tuning only; results do not depend on it)
   int x_rows = 4;    // rows per workgroup of the x passes (1, 2, 4; lowered to fit)
   int yz_cols = 16;  // pencils per workgroup of the y / z passes (1..16, lowered to fit)
+  int mid_pairs = 1; // fused z pass: 1 one field pair per workgroup, 0 all six fields
 };
 
 enum MediumKind { kMedNone = 0, kMedChiral = 1, kMedPseudo = 2 };

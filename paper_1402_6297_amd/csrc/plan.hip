@@ -317,6 +317,10 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
         return set_error(p, NSF_E_ARG, "NSF_OPT_YZ_COLS takes 1, 2, 4, 8 or 16");
       p->geom.yz_cols = value;
       return NSF_OK;
+    case NSF_OPT_MID_PAIRS:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_MID_PAIRS takes 0 or 1");
+      p->geom.mid_pairs = value;
+      return NSF_OK;
     case NSF_OPT_CG_GRAPH:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_GRAPH takes 0 or 1");
       p->opt_cg_graph = value;

@@ -1,9 +1,10 @@
 // Launch-tiling autotuner: times the A_r apply of a plan under each candidate
 // tiling of its FFT passes and keeps the fastest.  The candidates are the pass
 // families (two-level register passes, generic LDS-staged passes, single-wave
-// x and z passes) and, for the two-level family, the workgroup tiles: pencils
-// per workgroup of the fused z pass, rows per workgroup of the x passes and
-// pencils per workgroup of the y / z passes.  Every candidate computes the same
+// x and z passes) and, for the two-level family, the workgroup tiles: one
+// field pair or all six fields per workgroup of the fused z pass and its
+// pencils per workgroup, rows per workgroup of the x passes and pencils per
+// workgroup of the y / z passes.  Every candidate computes the same
 // transforms; only the arithmetic order of the CG reductions (partials per
 // workgroup) can change, so results agree to rounding.
 #include <algorithm>
@@ -15,7 +16,7 @@ namespace nsf {
 namespace {
 
 struct Tiling {
-  int path, mid, xr, yz;
+  int path, mid, xr, yz, pairs;
 };
 
 void apply_tiling(nsf_plan p, const Tiling& t) {
@@ -23,6 +24,7 @@ void apply_tiling(nsf_plan p, const Tiling& t) {
   p->opt_mid_cols = t.mid;
   p->geom.x_rows = t.xr;
   p->geom.yz_cols = t.yz;
+  p->geom.mid_pairs = t.pairs;
 }
 
 // Average milliseconds of one A_r apply (after two untimed ones).
@@ -59,20 +61,22 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
   if (rc) return rc;
   const Geom& g = p->geom;
   const long long len = 4 * g.n;
-  const Tiling dflt{0, 8, 4, 16};
+  const Tiling dflt{0, 8, 4, 16, 1};
   std::vector<Tiling> cand{dflt};
   const bool fast = fast_axis(g.n1) || fast_axis(g.n2) || fast_axis(g.n3);
   if (fast)
-    for (int mid : {4, 8, 16})
-      for (int xr : {1, 2, 4})
-        for (int yz : {4, 8, 16}) {
-          const Tiling t{0, mid, xr, yz};
-          if (!(t.mid == dflt.mid && t.xr == dflt.xr && t.yz == dflt.yz)) cand.push_back(t);
-        }
-  cand.push_back(Tiling{1, 8, 4, 16});
-  if (wave_axis(g.n1) || wave_mid_ok(g)) cand.push_back(Tiling{2, 8, 4, 16});
+    for (int pairs : {1, 0})
+      for (int mid : {4, 8, 16})
+        for (int xr : {1, 2, 4})
+          for (int yz : {4, 8, 16}) {
+            const Tiling t{0, mid, xr, yz, pairs};
+            if (!(t.mid == dflt.mid && t.xr == dflt.xr && t.yz == dflt.yz && t.pairs == dflt.pairs))
+              cand.push_back(t);
+          }
+  cand.push_back(Tiling{1, 8, 4, 16, 1});
+  if (wave_axis(g.n1) || wave_mid_ok(g)) cand.push_back(Tiling{2, 8, 4, 16, 1});
 
-  const Tiling saved{p->opt_fft_path, p->opt_mid_cols, g.x_rows, g.yz_cols};
+  const Tiling saved{p->opt_fft_path, p->opt_mid_cols, g.x_rows, g.yz_cols, g.mid_pairs};
   double2* buf = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto cleanup = [&]() {
@@ -117,6 +121,7 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
     result->mid_cols = best.mid;
     result->x_rows = best.xr;
     result->yz_cols = best.yz;
+    result->mid_pairs = best.pairs;
     result->us_best = best_ms * 1e3;
     result->us_default = dflt_ms * 1e3;
     result->tried = tried;

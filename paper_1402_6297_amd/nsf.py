@@ -33,6 +33,7 @@ NSF_OPT_MID_COLS = 2
 NSF_OPT_CG_GRAPH = 3
 NSF_OPT_X_ROWS = 4
 NSF_OPT_YZ_COLS = 5
+NSF_OPT_MID_PAIRS = 6
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",
@@ -58,7 +59,7 @@ class nsf_stats(C.Structure):
 
 class nsf_tune(C.Structure):
     _fields_ = [("fft_path", C.c_int), ("mid_cols", C.c_int), ("x_rows", C.c_int), ("yz_cols", C.c_int),
-                ("us_best", C.c_double), ("us_default", C.c_double), ("tried", C.c_int)]
+                ("mid_pairs", C.c_int), ("us_best", C.c_double), ("us_default", C.c_double), ("tried", C.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

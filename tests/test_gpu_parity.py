@@ -417,19 +417,23 @@ def test_cg_graph_replay_matches_eager(batched):
     assert mv0 == mv1 and it0 == it1
 
 
-TILINGS = [(4, 1, 1), (4, 2, 4), (8, 4, 8), (16, 1, 16), (2, 2, 2), (1, 4, 16)]
+TILINGS = [(4, 1, 1, 1), (4, 2, 4, 0), (8, 4, 8, 1), (16, 1, 16, 0), (2, 2, 2, 1), (1, 4, 16, 0),
+           (16, 4, 16, 1), (8, 4, 16, 0)]
 
 
-@pytest.mark.parametrize("mid,xr,yz", TILINGS, ids=[f"mid{a}-x{b}-yz{c}" for a, b, c in TILINGS])
+@pytest.mark.parametrize("mid,xr,yz,pairs", TILINGS, ids=[f"mid{a}-x{b}-yz{c}-pairs{d}" for a, b, c, d in TILINGS])
 @pytest.mark.parametrize("grid,k,kind", [((64, 16, 48), (0.3, 0.0, 0.2), "chiral"),
                                          ((16, 32, 64), (0.1, 0.2, 0.3), "pseudo_xz"),
-                                         ((96, 16, 16), (0.1, 0.4, 0.3), "noise")])
-def test_Ar_every_tiling_matches_oracle(grid, k, kind, mid, xr, yz):
+                                         ((96, 16, 16), (0.1, 0.4, 0.3), "noise"),
+                                         ((32, 64, 128), (0.2, 0.1, 0.4), "pseudo_xy"),
+                                         ((48, 32, 16), (0.3, 0.2, 0.1), "pseudo_yz")])
+def test_Ar_every_tiling_matches_oracle(grid, k, kind, mid, xr, yz, pairs):
     """Each workgroup tiling the autotuner may pick computes the same A_r."""
     n = grid[0] * grid[1] * grid[2]
     eps, gam, tens, pair = _medium(kind, grid)
     u = media.random_vector(4 * n, 6)
     with nsf.Plan(grid, k) as P:
+        P.set_option(nsf.NSF_OPT_MID_PAIRS, pairs)
         P.set_option(nsf.NSF_OPT_MID_COLS, mid)
         P.set_option(nsf.NSF_OPT_X_ROWS, xr)
         P.set_option(nsf.NSF_OPT_YZ_COLS, yz)
