@@ -98,7 +98,7 @@ enum {
                             2: single-wave passes (E'/H' lane halves) for the
                                x and fused z passes where possible          */
   NSF_OPT_MID_COLS = 2,  /* pencils per workgroup of the fused z pass: 1..16,
-                            power of two (default 8)                          */
+                            power of two (default 16)                         */
   NSF_OPT_CG_GRAPH = 3,  /* 1: the eigensolver captures one CG iteration of all
                             unfinished instances as a HIP graph and replays it
                             (default); 0: launches every kernel each iteration */
@@ -119,14 +119,14 @@ int nsf_plan_set_option(nsf_plan plan, int option, int value);
 
 /*
  * Autotuner of the FFT pass family and workgroup tiles.  Times reps A_r
- * applies (after two untimed ones) under each candidate: the two-level
- * register passes with NSF_OPT_MID_PAIRS in {1, 0}, NSF_OPT_MID_COLS in
- * {4, 8, 16}, NSF_OPT_X_ROWS in {1, 2, 4} and NSF_OPT_YZ_COLS in {4, 8, 16};
- * the generic LDS-staged passes;
- * the single-wave passes where the grid allows them.  Keeps the fastest as the
- * plan's options.  Needs a medium (NSF_E_STATE); allocates two 4n scratch
- * vectors for the call (NSF_E_NOMEM).  Results of later calls agree with the
- * defaults to rounding.  Synchronises the stream.
+ * applies (after two untimed ones) per candidate, by coordinate descent from
+ * the defaults (two sweeps): NSF_OPT_FFT_PATH over the families the grid
+ * allows, then for the two-level family NSF_OPT_MID_PAIRS {1, 0},
+ * NSF_OPT_MID_COLS {4, 8, 16}, NSF_OPT_X_ROWS {1, 2, 4} and NSF_OPT_YZ_COLS
+ * {4, 8, 16}.  Keeps the fastest as the plan's
+ * options.  Needs a medium (NSF_E_STATE); allocates two 4n scratch vectors
+ * for the call (NSF_E_NOMEM).  Results of later calls agree with the defaults
+ * to rounding.  Synchronises the stream.
  *   reps    1..1000 timed applies per candidate
  *   result  nullable; the chosen options, the average apply time with them and
  *           with the defaults (microseconds), and the candidates timed

@@ -212,9 +212,17 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
 // In every pair the step is e' = (eps e - i g h) s, h' = (i g e + h) s with
 // s = 1/(n (eps - g^2)), where g = gamma for a coupled pair and g = 0 for the
 // uncoupled one.  One workgroup transforms one pair of P z-pencil columns, so
-// its LDS tile is a third of the six-field tile.  The three pairs of a tile
-// are dispatched to the same XCD one after another (when the tile count is a
-// multiple of 8), so the medium they all read is served from that XCD's L2.
+// its LDS tile is a third of the six-field tile; the three pairs of a tile go
+// to the same XCD one after another (when the tile count is a multiple of 8),
+// so the medium they all read is served from that XCD's L2.
+//
+// With z = n2 + N2 n1 and frequency k = k1 + N1 k2, the inverse transform
+// leaves each thread with its field at the positions k1 + N1 k2 of its k1 and
+// every k2.  The constitutive step runs there (the partner field comes through
+// LDS), and the forward transform starts from the same distribution: a radix-N2
+// transform over k2 in registers, the twiddle w^-(k1 m2), one LDS exchange, and
+// a radix-N1 transform over k1 that yields the outputs m2 + N2 m1 at exactly the
+// addresses the thread loaded.
 template <int N1, int N2, bool BT = false>
 __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView med,
                                                  double2* __restrict__ fld, int P, const int* skip,
@@ -271,10 +279,12 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
   const long long n = g.n;
   double2* F = fld + (h == 0 ? fe : fh) * n + base + p;
   double2* T = tile + h * N * P + p;
+  const double2* Tq = tile + (1 - h) * N * P + p;  // the partner field
+  const double2* eg = med.eg + base + p;
   double2 v[N1];
 #pragma unroll
   for (int n1 = 0; n1 < N1; ++n1) v[n1] = F[(n2 + N2 * n1) * stride];
-  __syncthreads();
+  __syncthreads();  // twiddles ready
   // inverse z
   step1<N1, N2, +1>(v, n2, twl);
 #pragma unroll
@@ -291,6 +301,7 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
     }
   }
   __syncthreads();
+  // constitutive step at this thread's positions k1 + N1 k2 (times 1/n)
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const int k1 = n2 + d * N2;
@@ -300,38 +311,45 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
     }
   }
   __syncthreads();
-  // constitutive step of the pair (times 1/n)
   const double inv_n = 1.0 / (double)n;
-  for (int vx = threadIdx.x; vx < P * N; vx += blockDim.x) {
-    const int pp = vx % P, j = vx / P;
-    const double2 eg = med.eg[base + j * stride + pp];
-    const double eps = eg.x, gm = coupled ? eg.y : 0.0;
-    const double sc = inv_n / (eps - gm * gm);
-    const double2 e = tile[j * P + pp], hh = tile[(N + j) * P + pp];
-    tile[j * P + pp] = cscale(csub(cscale(e, eps), cmuli(cscale(hh, gm))), sc);
-    tile[(N + j) * P + pp] = cscale(cadd(cmuli(cscale(e, gm)), hh), sc);
-  }
-  __syncthreads();
-  // forward z
-#pragma unroll
-  for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[(n2 + N2 * n1) * P];
-  __syncthreads();
-  step1<N1, N2, -1>(v, n2, twl);
-#pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) T[(n2 + N2 * k1) * P] = v[k1];
-  __syncthreads();
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const int k1 = n2 + d * N2;
     if (k1 < N1) {
-      double2 u[N2];
 #pragma unroll
-      for (int m = 0; m < N2; ++m) u[m] = T[(m + N2 * k1) * P];
-      reg_dft<N2, -1>(u);
-#pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) F[(k1 + N1 * k2) * stride] = u[k2];
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int z = k1 + N1 * k2;
+        const double2 m = eg[z * stride];
+        const double eps = m.x, gm = coupled ? m.y : 0.0;
+        const double sc = inv_n / (eps - gm * gm);
+        const double2 other = Tq[z * P];
+        const double2 own = out[d][k2];
+        out[d][k2] = (h == 0) ? cscale(csub(cscale(own, eps), cmuli(cscale(other, gm))), sc)
+                              : cscale(cadd(cmuli(cscale(other, gm)), own), sc);
+      }
     }
   }
+  __syncthreads();  // partner values read before the tile is reused
+  // forward z: radix N2 over k2, twiddle, exchange, radix N1 over k1
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+      reg_dft<N2, -1>(out[d]);
+#pragma unroll
+      for (int m2 = 0; m2 < N2; ++m2) {
+        double2 x = out[d][m2];
+        if (k1 > 0 && m2 > 0) x = cmul(x, cconj(twl[k1 * m2]));
+        T[(m2 * N1 + k1) * P] = x;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) v[k1] = T[(n2 * N1 + k1) * P];
+  reg_dft<N1, -1>(v);
+#pragma unroll
+  for (int m1 = 0; m1 < N1; ++m1) F[(n2 + N2 * m1) * stride] = v[m1];
 }
 
 // ------------------------------------------------------------- x passes
@@ -682,9 +700,10 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
     int P = pick_cols(g.n1, P_want);
     while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lds_limit())) P /= 2;
     if (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lds_limit()) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(3 * (g.n1 / P) * g.n2), 1, (unsigned)ninst);
+    const unsigned items = (unsigned)(3 * (g.n1 / P) * g.n2);
     const dim3 block(2 * P * cfg.N2);
     const size_t lds = sizeof(double2) * (size_t)(N + 2 * N * P);
+    const dim3 grid(items, 1, (unsigned)ninst);
 #define L_PAIR(A, B)                                                                                 \
   if (lds > 65536) { /* opt in once per kernel, to the device limit (not a stream operation) */     \
     static const hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_pair<A, B>), \

@@ -288,7 +288,7 @@ struct nsf_plan_s {
 
   // options (nsf_plan_set_option)
   int opt_fft_path = 0;     // 0 auto, 1 generic LDS-staged, 2 two-level without single-wave
-  int opt_mid_cols = 8;     // pencils per workgroup of the fused z pass
+  int opt_mid_cols = 16;    // pencils per workgroup of the fused z pass
   int opt_cg_graph = 1;     // CG iterations of the eigensolver replayed from a HIP graph
 
   std::string last_error;

@@ -1,12 +1,13 @@
-// Launch-tiling autotuner: times the A_r apply of a plan under each candidate
-// tiling of its FFT passes and keeps the fastest.  The candidates are the pass
-// families (two-level register passes, generic LDS-staged passes, single-wave
-// x and z passes) and, for the two-level family, the workgroup tiles: one
-// field pair or all six fields per workgroup of the fused z pass and its
-// pencils per workgroup, rows per workgroup of the x passes and pencils per
-// workgroup of the y / z passes.  Every candidate computes the same
-// transforms; only the arithmetic order of the CG reductions (partials per
-// workgroup) can change, so results agree to rounding.
+// Launch-tiling autotuner: times the A_r apply of a plan under candidate
+// tilings of its FFT passes and keeps the fastest.  The knobs are the pass
+// family (two-level register passes, generic LDS-staged passes, single-wave x
+// and z passes) and, for the two-level family, the workgroup tiles: one field
+// pair or all six fields per workgroup of the fused z pass and its pencils per
+// workgroup, rows per workgroup of the x passes and pencils per workgroup of
+// the y / z passes.  The search is
+// coordinate descent from the defaults, two sweeps over the knobs.  Every
+// candidate computes the same transforms; only the arithmetic order of the CG
+// reductions (partials per workgroup) can change, so results agree to rounding.
 #include <algorithm>
 #include <vector>
 
@@ -17,6 +18,9 @@ namespace {
 
 struct Tiling {
   int path, mid, xr, yz, pairs;
+  bool operator==(const Tiling& o) const {
+    return path == o.path && mid == o.mid && xr == o.xr && yz == o.yz && pairs == o.pairs;
+  }
 };
 
 void apply_tiling(nsf_plan p, const Tiling& t) {
@@ -61,21 +65,9 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
   if (rc) return rc;
   const Geom& g = p->geom;
   const long long len = 4 * g.n;
-  const Tiling dflt{0, 8, 4, 16, 1};
-  std::vector<Tiling> cand{dflt};
+  const Tiling dflt{0, 16, 4, 16, 1};
   const bool fast = fast_axis(g.n1) || fast_axis(g.n2) || fast_axis(g.n3);
-  if (fast)
-    for (int pairs : {1, 0})
-      for (int mid : {4, 8, 16})
-        for (int xr : {1, 2, 4})
-          for (int yz : {4, 8, 16}) {
-            const Tiling t{0, mid, xr, yz, pairs};
-            if (!(t.mid == dflt.mid && t.xr == dflt.xr && t.yz == dflt.yz && t.pairs == dflt.pairs))
-              cand.push_back(t);
-          }
-  cand.push_back(Tiling{1, 8, 4, 16, 1});
-  if (wave_axis(g.n1) || wave_mid_ok(g)) cand.push_back(Tiling{2, 8, 4, 16, 1});
-
+  const bool wave = wave_axis(g.n1) || wave_mid_ok(g);
   const Tiling saved{p->opt_fft_path, p->opt_mid_cols, g.x_rows, g.yz_cols, g.mid_pairs};
   double2* buf = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -100,20 +92,63 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
     return fail(set_error(p, NSF_E_HIP, "autotune: event creation failed"));
   if (launch_randn(buf, len, 0x5eedULL, p->stream) != hipSuccess)
     return fail(set_error(p, NSF_E_HIP, "autotune: launch failed"));
-  double best_ms = 0, dflt_ms = 0;
-  Tiling best = dflt;
-  int tried = 0;
-  for (const Tiling& t : cand) {
+  std::vector<std::pair<Tiling, double>> seen;
+  auto measure = [&](const Tiling& t, double* ms) -> int {
+    for (auto& sm : seen)
+      if (sm.first == t) {
+        *ms = sm.second;
+        return NSF_OK;
+      }
     apply_tiling(p, t);
+    const int r = time_apply(p, buf, buf + len, reps, e0, e1, ms);
+    if (r) return r;
+    seen.emplace_back(t, *ms);
+    return NSF_OK;
+  };
+  Tiling best = dflt;
+  double best_ms = 0, dflt_ms = 0;
+  if ((rc = measure(dflt, &dflt_ms))) return fail(rc);
+  best_ms = dflt_ms;
+  auto try_one = [&](Tiling t) -> int {
     double ms = 0;
-    if ((rc = time_apply(p, buf, buf + len, reps, e0, e1, &ms))) return fail(rc);
-    ++tried;
-    if (tried == 1) dflt_ms = ms;
-    if (tried == 1 || ms < best_ms) {
+    const int r = measure(t, &ms);
+    if (r) return r;
+    if (ms < best_ms) {
       best_ms = ms;
       best = t;
     }
+    return NSF_OK;
+  };
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    for (int path : {0, 1, 2}) {
+      if ((path == 0 && !fast) || (path == 2 && !wave)) continue;
+      Tiling t = best;
+      t.path = path;
+      if ((rc = try_one(t))) return fail(rc);
+    }
+    if (best.path != 0) continue;  // the remaining knobs tile the two-level passes
+    for (int pairs : {1, 0}) {
+      Tiling t = best;
+      t.pairs = pairs;
+      if ((rc = try_one(t))) return fail(rc);
+    }
+    for (int mid : {4, 8, 16}) {
+      Tiling t = best;
+      t.mid = mid;
+      if ((rc = try_one(t))) return fail(rc);
+    }
+    for (int xr : {1, 2, 4}) {
+      Tiling t = best;
+      t.xr = xr;
+      if ((rc = try_one(t))) return fail(rc);
+    }
+    for (int yz : {4, 8, 16}) {
+      Tiling t = best;
+      t.yz = yz;
+      if ((rc = try_one(t))) return fail(rc);
+    }
   }
+  const int tried = (int)seen.size();
   apply_tiling(p, best);
   cleanup();
   if (result) {

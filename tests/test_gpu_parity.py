@@ -418,7 +418,7 @@ def test_cg_graph_replay_matches_eager(batched):
 
 
 TILINGS = [(4, 1, 1, 1), (4, 2, 4, 0), (8, 4, 8, 1), (16, 1, 16, 0), (2, 2, 2, 1), (1, 4, 16, 0),
-           (16, 4, 16, 1), (8, 4, 16, 0)]
+           (16, 4, 16, 1), (8, 4, 16, 0), (1, 2, 8, 1)]
 
 
 @pytest.mark.parametrize("mid,xr,yz,pairs", TILINGS, ids=[f"mid{a}-x{b}-yz{c}-pairs{d}" for a, b, c, d in TILINGS])
