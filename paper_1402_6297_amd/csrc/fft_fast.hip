@@ -387,38 +387,51 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
     cg_al = cg.st->alpha;
     cg_be = cg.st->beta;
   }
-  // synthesis of the coefficient fields, one frequency per thread and step
-  for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
+  // synthesis of the coefficient fields: this thread's frequencies are
+  // e = threadIdx.x + it * blockDim.x (blockDim = F R N2 for R N frequencies)
+  constexpr int IT = (N1 + F - 1) / F;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * blockDim.x;
+    if (e >= R * N) break;
     const int r = e / N, i1 = e - r * N;
     const long long row = row0 + r;
     if (row >= rows) continue;
     const int i2 = (int)(row % g.n2), i3 = (int)(row / g.n2);
     const long long f = row * N + i1;
-    Basis B;
-    basis_at(t.lam, g, i1, i2, i3, B);
     double2 yv[4];
     if (CG) {
-      // CG recurrences of the previous iteration, then this iteration's p
+      // CG recurrences of the previous iteration, then this iteration's p;
+      // every load is issued before the stores (which may alias them)
+      double2 po[4], qo[4], ro[4], xo[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const long long o = b * n + f;
-        const double2 po = cg.p[o];
-        if (cg_iter > 0) {
-          const double2 qo = cg.q[o];
-          double2 rv = cg.r[o], xv = cg.x[o];
-          rv = make_double2(rv.x - cg_al * qo.x, rv.y - cg_al * qo.y);
-          xv = make_double2(xv.x + cg_al * po.x, xv.y + cg_al * po.y);
-          const double2 pn = make_double2(rv.x + cg_be * po.x, rv.y + cg_be * po.y);
+      for (int b = 0; b < 4; ++b) po[b] = cg.p[b * n + f];
+      if (cg_iter > 0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          qo[b] = cg.q[b * n + f];
+          ro[b] = cg.r[b * n + f];
+          xo[b] = cg.x[b * n + f];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const long long o = b * n + f;
+          const double2 rv = make_double2(ro[b].x - cg_al * qo[b].x, ro[b].y - cg_al * qo[b].y);
+          const double2 xv = make_double2(xo[b].x + cg_al * po[b].x, xo[b].y + cg_al * po[b].y);
+          const double2 pn = make_double2(rv.x + cg_be * po[b].x, rv.y + cg_be * po[b].y);
           cg.r[o] = rv;
           cg.x[o] = xv;
           cg.p[o] = pn;
           rr_acc[0] += cabs2(rv);
           yv[b] = pn;
-        } else {
-          yv[b] = po;
         }
+      } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) yv[b] = po[b];
       }
     }
+    Basis B;
+    basis_at(t.lam, g, i1, i2, i3, B);
     if (PART == kPartBoth || PART == kPartP) {
       const double2 ya = CG ? yv[0] : y[f], yb = CG ? yv[1] : y[n + f];
 #pragma unroll
@@ -540,13 +553,25 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
   }
   __syncthreads();
   double acc[3] = {0.0, 0.0, 0.0};  // Re p^*q, |q|^2, Re r^*q (fused CG)
-  // projection, one frequency per thread and step
-  for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
+  // projection: this thread's frequencies e = threadIdx.x + it * blockDim.x
+  constexpr int IT = (N1 + F - 1) / F;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * blockDim.x;
+    if (e >= R * N) break;
     const int rr = e / N, i1 = e - rr * N;
     const long long row = row0 + rr;
     if (row >= rows) continue;
     const int i2 = (int)(row % g.n2), i3 = (int)(row / g.n2);
     const long long f = row * N + i1;
+    double2 pv[4], rv[4];  // fused CG: loaded before the stores of q (which may alias them)
+    if (CG) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        pv[b] = cg.p[b * n + f];
+        rv[b] = cg.r[b * n + f];
+      }
+    }
     Basis B;
     basis_at(t.lam, g, i1, i2, i3, B);
     double2 oa = make_double2(0, 0), ob = make_double2(0, 0);
@@ -576,11 +601,9 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
         const double2 qv[4] = {oa, ob, oc, od};
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const long long ofs = b * n + f;
-          const double2 pv = cg.p[ofs], rv = cg.r[ofs];
-          acc[0] += pv.x * qv[b].x + pv.y * qv[b].y;
+          acc[0] += pv[b].x * qv[b].x + pv[b].y * qv[b].y;
           acc[1] += cabs2(qv[b]);
-          acc[2] += rv.x * qv[b].x + rv.y * qv[b].y;
+          acc[2] += rv[b].x * qv[b].x + rv[b].y * qv[b].y;
         }
       }
     }
