@@ -106,9 +106,12 @@ enum {
                             1, 2 or 4 (default 4; lowered where it does not fit) */
   NSF_OPT_YZ_COLS = 5,   /* pencils per workgroup of the two-level y / z passes:
                             1..16, power of two (default 16; lowered to fit)    */
-  NSF_OPT_MID_PAIRS = 6  /* fused z pass of the two-level path: 1 one coupled
+  NSF_OPT_MID_PAIRS = 6, /* fused z pass of the two-level path: 1 one coupled
                             (E', H') field pair per workgroup (default), 0 all
                             six fields per workgroup                           */
+  NSF_OPT_CG_START = 7   /* eigensolver inner CG: 1 starts from the A_r-Galerkin
+                            solution in the span of the Lanczos basis (default),
+                            0 from zero; the Lanczos direction is the same     */
 };
 
 /*

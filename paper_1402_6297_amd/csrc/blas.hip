@@ -5,6 +5,8 @@
 // sums a fixed strided slice, waves reduce with butterfly shuffles and a
 // single workgroup folds the per-workgroup partials in a fixed order.  No
 // floating-point atomics are used.
+#include <algorithm>
+
 #include "nsf_internal.h"
 
 namespace nsf {
@@ -61,19 +63,30 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double2* partial, 
 }
 
 // ------------------------------------------------------------------ CG
+// x = 0, r = p = b - sum_i c_i AV_i (the residual of the start x0 = sum_i c_i V_i
+// when AV_i = A V_i; no sum when m = 0); partials of (|b|^2, |r|^2).
 __global__ __launch_bounds__(kRedThreads) void k_cg_init(const double2* __restrict__ b,
                                                          double2* __restrict__ x,
                                                          double2* __restrict__ r,
                                                          double2* __restrict__ p, long long len,
-                                                         double2* partial) {
+                                                         double2* partial,
+                                                         const double2* __restrict__ AV, long long ld,
+                                                         int m, const double2* __restrict__ c) {
+  __shared__ double2 cs[512];
+  for (int i = threadIdx.x; i < m; i += kRedThreads) cs[i] = c[i];
+  __syncthreads();
   double2 acc = make_double2(0, 0);
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < len;
        i += (long long)gridDim.x * kRedThreads) {
     const double2 v = b[i];
+    double2 rv = v;
+#pragma unroll 8
+    for (int j = 0; j < m; ++j) rv = csub(rv, cmul(cs[j], AV[j * ld + i]));
     x[i] = make_double2(0, 0);
-    r[i] = v;
-    p[i] = v;
+    r[i] = rv;
+    p[i] = rv;
     acc.x += cabs2(v);
+    acc.y += cabs2(rv);
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -86,7 +99,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_init_final(const double2* pa
   if (threadIdx.x == 0) {
     const double bb = s.x;
     st->bb = bb;
-    st->rr = bb;
+    st->rr = s.y;
     st->thresh = rtol * rtol * bb;
     st->alpha = 0;
     st->beta = 0;
@@ -94,9 +107,11 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_init_final(const double2* pa
     st->maxit = maxit;
     st->status = NSF_OK;
     st->done = 0;
-    if (!(bb > 0.0)) {
+    if (!(bb > 0.0) || !(s.y == s.y)) {
       st->done = 1;
       st->status = (bb == 0.0) ? NSF_OK : NSF_E_BREAKDOWN;  // zero rhs, or NaN
+    } else if (s.y <= st->thresh) {
+      st->done = 1;  // the start already solves the system to the tolerance
     } else if (maxit <= 0) {
       st->done = 1;
       st->status = NSF_NOT_CONVERGED;
@@ -239,27 +254,32 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, in
 }
 
 // ------------------------------------------------------- multi-vector ops
-constexpr int kDotChunk = 4;  // basis vectors per workgroup of the multi-dot
+// Partial sums of V[i]^* w for the kDotChunk basis vectors of one workgroup
+// row: each element of w is read once per chunk, and the loads of one element
+// for every vector of the chunk are issued together.
+constexpr int kDotChunk = 4;
 
 __global__ __launch_bounds__(kRedThreads) void k_multi_dot(const double2* __restrict__ V,
                                                            long long ld, int m,
                                                            const double2* __restrict__ w,
                                                            long long len, double2* partial) {
   const int i0 = blockIdx.y * kDotChunk;
+  const int cnt = min(kDotChunk, m - i0);
   double2 acc[kDotChunk];
 #pragma unroll
   for (int c = 0; c < kDotChunk; ++c) acc[c] = make_double2(0, 0);
+  const double2* Vc = V + (long long)i0 * ld;
   for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < len;
        e += (long long)gridDim.x * kRedThreads) {
     const double2 we = w[e];
 #pragma unroll
     for (int c = 0; c < kDotChunk; ++c)
-      if (i0 + c < m) acc[c] = cadd(acc[c], cmulc(V[(i0 + c) * ld + e], we));
+      if (c < cnt) acc[c] = cadd(acc[c], cmulc(Vc[c * ld + e], we));
   }
 #pragma unroll
   for (int c = 0; c < kDotChunk; ++c) {
     const double2 s = block_sum(acc[c]);
-    if (threadIdx.x == 0 && i0 + c < m) partial[(long long)(i0 + c) * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0 && c < cnt) partial[(long long)(i0 + c) * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -269,10 +289,14 @@ __global__ __launch_bounds__(kRedThreads) void k_multi_dot_final(const double2* 
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// w -= sum_i c_i V[i] and, when V2 is given, z -= sum_i c_i V2[i] (the same
+// coefficients), eight basis vectors per unrolled step.
 __global__ __launch_bounds__(kRedThreads) void k_multi_axpy(const double2* __restrict__ V,
+                                                            const double2* __restrict__ V2,
                                                             long long ld, int m,
                                                             const double2* __restrict__ c,
                                                             double2* __restrict__ w,
+                                                            double2* __restrict__ z,
                                                             long long len) {
   __shared__ double2 cs[512];
   for (int i = threadIdx.x; i < m; i += kRedThreads) cs[i] = c[i];
@@ -280,13 +304,41 @@ __global__ __launch_bounds__(kRedThreads) void k_multi_axpy(const double2* __res
   for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < len;
        e += (long long)gridDim.x * kRedThreads) {
     double2 acc = w[e];
-    for (int i = 0; i < m; ++i) acc = csub(acc, cmul(cs[i], V[i * ld + e]));
+    double2 acz = V2 ? z[e] : make_double2(0, 0);
+#pragma unroll 8
+    for (int i = 0; i < m; ++i) {
+      acc = csub(acc, cmul(cs[i], V[i * ld + e]));
+      if (V2) acz = csub(acz, cmul(cs[i], V2[i * ld + e]));
+    }
     w[e] = acc;
+    if (V2) z[e] = acz;
   }
 }
 
-// In-place V[:, 0:k] = V[:, 0:m] S for a slab of `cols` elements at a time:
-// the slab of all m vectors is read into LDS before any of it is overwritten.
+// In place V[:, 0:k] = V[:, 0:m] S with each thread holding one element of all
+// m vectors in registers (m <= MM): a thread reads element e of every vector
+// before it writes element e of any, and no other thread touches element e.
+template <int MM>
+__global__ __launch_bounds__(kRedThreads) void k_rotate_reg(double2* V, long long ld, int m, int k,
+                                                            const double2* __restrict__ S,
+                                                            long long len) {
+  for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < len;
+       e += (long long)gridDim.x * kRedThreads) {
+    double2 x[MM];
+#pragma unroll
+    for (int i = 0; i < MM; ++i) x[i] = (i < m) ? V[i * ld + e] : make_double2(0, 0);
+    for (int c = 0; c < k; ++c) {
+      double2 acc = make_double2(0, 0);
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+        if (i < m) acc = cadd(acc, cmul(x[i], S[c * m + i]));
+      V[c * ld + e] = acc;
+    }
+  }
+}
+
+// The same for any m: a slab of `cols` elements of all m vectors is read into
+// LDS before any of it is overwritten.
 __global__ __launch_bounds__(kRedThreads) void k_rotate(double2* V, long long ld, int m, int k,
                                                         const double2* __restrict__ S,
                                                         long long len, int kRotCols) {
@@ -388,9 +440,11 @@ hipError_t launch_reduce_partials(const double2* partial, int nparts, double2* o
 }
 
 hipError_t launch_cg_init(const double2* b, double2* x, double2* r, double2* p, long long len,
-                          double2* partial, CgState* st, double rtol, int maxit, hipStream_t s) {
+                          double2* partial, CgState* st, double rtol, int maxit, hipStream_t s,
+                          const double2* AV, long long ld, int m, const double2* c) {
+  if (m < 0 || m > 512 || (m > 0 && (!AV || !c))) return hipErrorInvalidValue;
   const int nb = red_grid(len);
-  hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, b, x, r, p, len, partial);
+  hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, b, x, r, p, len, partial, AV, ld, m, c);
   hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kRedThreads), 0, s, partial, nb, st, rtol, maxit);
   return hipGetLastError();
 }
@@ -432,30 +486,43 @@ hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipS
 hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2* w, long long len,
                             double2* partial, double2* out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  int nb = red_grid(len);
-  if (nb > 256) nb = 256;
-  const dim3 grid(nb, (m + kDotChunk - 1) / kDotChunk);
+  // about 4096 workgroups in all, within the partial-sum slots (m x nb)
+  const int rows = (m + kDotChunk - 1) / kDotChunk;
+  long long nb = std::min<long long>((len + kRedThreads - 1) / kRedThreads, 4096 / rows);
+  nb = std::min<long long>(nb, kPartialSlots / m);
+  if (nb < 1) nb = 1;
+  const dim3 grid((unsigned)nb, rows);
   hipLaunchKernelGGL(k_multi_dot, grid, dim3(kRedThreads), 0, s, V, ld, m, w, len, partial);
-  hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(kRedThreads), 0, s, partial, nb, out);
+  hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(kRedThreads), 0, s, partial, (int)nb, out);
   return hipGetLastError();
 }
 
 hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
-                             long long len, hipStream_t s) {
+                             long long len, hipStream_t s, const double2* V2, double2* z) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_multi_axpy, dim3(ew_grid(len)), dim3(kRedThreads), 0, s, V, ld, m, c, w, len);
+  if (m > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_multi_axpy, dim3(ew_grid(len)), dim3(kRedThreads), 0, s, V, V2, ld, m, c, w, z, len);
   return hipGetLastError();
 }
 
 hipError_t launch_rotate(double2* V, long long ld, int m, int k, const double2* S, long long len,
                          hipStream_t s) {
-  int cols = 4096 / m;
-  if (cols > 32) cols = 32;
-  if (cols < 1) cols = 1;
-  const long long blocks = (len + cols - 1) / cols;
-  const size_t lds = sizeof(double2) * (size_t)m * cols;
-  hipLaunchKernelGGL(k_rotate, dim3((unsigned)blocks), dim3(kRedThreads), lds, s, V, ld, m, k, S, len,
-                     cols);
+  if (m <= 0 || k <= 0) return hipSuccess;
+  const dim3 g(ew_grid(len)), b(kRedThreads);
+  if (m <= 16) {
+    hipLaunchKernelGGL(k_rotate_reg<16>, g, b, 0, s, V, ld, m, k, S, len);
+  } else if (m <= 32) {
+    hipLaunchKernelGGL(k_rotate_reg<32>, g, b, 0, s, V, ld, m, k, S, len);
+  } else if (m <= 48) {
+    hipLaunchKernelGGL(k_rotate_reg<48>, g, b, 0, s, V, ld, m, k, S, len);
+  } else {
+    int cols = 4096 / m;
+    if (cols > 32) cols = 32;
+    if (cols < 1) cols = 1;
+    const long long blocks = (len + cols - 1) / cols;
+    const size_t lds = sizeof(double2) * (size_t)m * cols;
+    hipLaunchKernelGGL(k_rotate, dim3((unsigned)blocks), b, lds, s, V, ld, m, k, S, len, cols);
+  }
   return hipGetLastError();
 }
 

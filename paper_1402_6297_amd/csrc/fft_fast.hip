@@ -353,7 +353,30 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
 }
 
 // ------------------------------------------------------------- x passes
-// R rows per workgroup; LDS tile[(c * R + r) * (N + 1) + e].
+// LDS rows of the x passes hold N elements each, row after row, with element e
+// of row r (r = row within the workgroup) at e ^ ((a (e >> s) + b r) & 15): an
+// XOR swizzle of the 16-element (256-byte) bank groups, chosen per split N1 x N2
+// so that the 16-lane groups of the strided second-radix reads, the first-radix
+// accesses and the synthesis / projection sweeps hit distinct 16-byte slots
+// (found by enumerating (s, a, b) against those access patterns).
+template <int N1, int N2>
+struct XSwz {
+  static constexpr int s = 3, a = 0, b = 0;
+};
+template <> struct XSwz<16, 8> { static constexpr int s = 3, a = 1, b = 8; };
+template <> struct XSwz<8, 8> { static constexpr int s = 3, a = 1, b = 8; };
+template <> struct XSwz<16, 16> { static constexpr int s = 4, a = 1, b = 0; };
+template <> struct XSwz<16, 6> { static constexpr int s = 5, a = 9, b = 7; };
+template <> struct XSwz<16, 3> { static constexpr int s = 3, a = 0, b = 12; };
+template <> struct XSwz<8, 4> { static constexpr int s = 3, a = 0, b = 5; };
+template <> struct XSwz<4, 4> { static constexpr int s = 3, a = 0, b = 5; };
+template <int N1, int N2>
+__device__ __forceinline__ int xpos(int e, int r) {
+  using W = XSwz<N1, N2>;
+  return e ^ ((((e >> W::s) * W::a) + r * W::b) & 15);
+}
+
+// R rows per workgroup; LDS tile[(c * R + r) * N + xpos(e, r)].
 template <int N1, int N2, int PART, bool CG = false, bool BT = false>
 __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const double2* __restrict__ y,
                                                       double2* __restrict__ fld, int R,
@@ -369,7 +392,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   }
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
-  constexpr int NP = N + 1;
+  constexpr int NP = N;
   constexpr int D = Split<N1, N2>::D;
   constexpr int F = (PART == kPartBoth) ? 6 : 3;
   extern __shared__ double2 sm[];
@@ -387,16 +410,11 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
     cg_al = cg.st->alpha;
     cg_be = cg.st->beta;
   }
-  // synthesis of the coefficient fields: this thread's frequencies are
-  // e = threadIdx.x + it * blockDim.x (blockDim = F R N2 for R N frequencies)
-  constexpr int IT = (N1 + F - 1) / F;
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int e = threadIdx.x + it * blockDim.x;
-    if (e >= R * N) break;
+  // synthesis of the coefficient fields at frequency slot e of the workgroup
+  auto synth = [&](int e) {
     const int r = e / N, i1 = e - r * N;
     const long long row = row0 + r;
-    if (row >= rows) continue;
+    if (row >= rows) return;
     const int i2 = (int)(row % g.n2), i3 = (int)(row / g.n2);
     const long long f = row * N + i1;
     double2 yv[4];
@@ -436,7 +454,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
       const double2 ya = CG ? yv[0] : y[f], yb = CG ? yv[1] : y[n + f];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
-        tile[(cc * R + r) * NP + i1] = csub(cmulc(B.pi1[cc], yb), cmulc(B.pi2[cc], ya));
+        tile[(cc * R + r) * NP + xpos<N1, N2>(i1, r)] = csub(cmulc(B.pi1[cc], yb), cmulc(B.pi2[cc], ya));
     }
     if (PART == kPartBoth || PART == kPartQ) {
       const long long o = (PART == kPartBoth) ? 2 * n : 0;
@@ -444,8 +462,21 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
       const double2 yc = CG ? yv[2] : y[o + f], yd = CG ? yv[3] : y[o + n + f];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
-        tile[((cb + cc) * R + r) * NP + i1] = cadd(cmul(B.pi1[cc], yc), cmul(B.pi2[cc], yd));
+        tile[((cb + cc) * R + r) * NP + xpos<N1, N2>(i1, r)] = cadd(cmul(B.pi1[cc], yc), cmul(B.pi2[cc], yd));
     }
+  };
+  // this thread's slots are e = threadIdx.x + it * blockDim.x (blockDim = F R N2
+  // for R N frequencies); with the CG update the loop is unrolled so that each
+  // slot's loads are issued together
+  if constexpr (CG) {
+    constexpr int IT = (N1 + F - 1) / F;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + it * blockDim.x;
+      if (e < R * N) synth(e);
+    }
+  } else {
+    for (int e = threadIdx.x; e < R * N; e += blockDim.x) synth(e);
   }
   if (CG) {
     block_sum_k<1>(rr_acc);
@@ -460,13 +491,13 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   double2 v[N1];
   if (active) {
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[n2 + N2 * n1];
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[xpos<N1, N2>(n2 + N2 * n1, r)];
     step1<N1, N2, +1>(v, n2, twl);
   }
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) T[n2 + N2 * k1] = v[k1];
+    for (int k1 = 0; k1 < N1; ++k1) T[xpos<N1, N2>(n2 + N2 * k1, r)] = v[k1];
   }
   __syncthreads();
   if (!active) return;
@@ -477,7 +508,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
     if (k1 < N1) {
       double2 u[N2];
 #pragma unroll
-      for (int m = 0; m < N2; ++m) u[m] = T[m + N2 * k1];
+      for (int m = 0; m < N2; ++m) u[m] = T[xpos<N1, N2>(m + N2 * k1, r)];
       reg_dft<N2, +1>(u);
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) out[k1 + N1 * k2] = u[k2];
@@ -500,7 +531,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
   }
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
-  constexpr int NP = N + 1;
+  constexpr int NP = N;
   constexpr int D = Split<N1, N2>::D;
   constexpr int F = (PART == kPartBoth) ? 6 : 3;
   extern __shared__ double2 sm[];
@@ -525,7 +556,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
   if (active) {
     step1<N1, N2, -1>(v, n2, twl);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) T[n2 + N2 * k1] = v[k1];
+    for (int k1 = 0; k1 < N1; ++k1) T[xpos<N1, N2>(n2 + N2 * k1, r)] = v[k1];
   }
   __syncthreads();
   double2 res[D][N2];
@@ -535,7 +566,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       const int k1 = n2 + d * N2;
       if (k1 < N1) {
 #pragma unroll
-        for (int m = 0; m < N2; ++m) res[d][m] = T[m + N2 * k1];
+        for (int m = 0; m < N2; ++m) res[d][m] = T[xpos<N1, N2>(m + N2 * k1, r)];
         reg_dft<N2, -1>(res[d]);
       }
     }
@@ -547,7 +578,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       const int k1 = n2 + d * N2;
       if (k1 < N1) {
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) T[k1 + N1 * k2] = res[d][k2];
+        for (int k2 = 0; k2 < N2; ++k2) T[xpos<N1, N2>(k1 + N1 * k2, r)] = res[d][k2];
       }
     }
   }
@@ -578,7 +609,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
     if (PART == kPartBoth || PART == kPartP) {
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
-        const double2 o = tile[(cc * R + rr) * NP + i1];
+        const double2 o = tile[(cc * R + rr) * NP + xpos<N1, N2>(i1, rr)];
         oa = csub(oa, cmul(B.pi2[cc], o));
         ob = cadd(ob, cmul(B.pi1[cc], o));
       }
@@ -591,7 +622,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       double2 oc = make_double2(0, 0), od = make_double2(0, 0);
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
-        const double2 o = tile[((cb + cc) * R + rr) * NP + i1];
+        const double2 o = tile[((cb + cc) * R + rr) * NP + xpos<N1, N2>(i1, rr)];
         oc = cadd(oc, cmulc(B.pi1[cc], o));
         od = cadd(od, cmulc(B.pi2[cc], o));
       }
@@ -673,7 +704,7 @@ int pick_cols(int n1, int want) {
 int x_rows_for(const Geom& g, const FastCfg& cfg, int F) {
   const int N = g.n1;
   int R = g.x_rows >= 4 ? 4 : (g.x_rows >= 2 ? 2 : 1);
-  while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * (N + 1)) * 16 > 64 * 1024)) R /= 2;
+  while (R > 1 && (F * R * cfg.N2 > 384 || (size_t)(N + F * R * N) * 16 > 64 * 1024)) R /= 2;
   return F * R * cfg.N2 > 384 ? 0 : R;
 }
 
@@ -782,7 +813,7 @@ hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, con
   const long long rows = (long long)g.n2 * g.n3;
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
-  const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+  const size_t lds = sizeof(double2) * (size_t)(N + F * R * N);
   if (insts && part != kPartBoth) return hipErrorInvalidValue;  // batched form covers both halves only
   const CgFuse none{};
 #define L_XI(A, B)                                                                                    \
@@ -814,7 +845,7 @@ hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, cons
   const long long rows = (long long)g.n2 * g.n3;
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   const dim3 block(F * R * cfg.N2);
-  const size_t lds = sizeof(double2) * (size_t)(N + F * R * (N + 1));
+  const size_t lds = sizeof(double2) * (size_t)(N + F * R * N);
   if (insts && part != kPartBoth) return hipErrorInvalidValue;  // batched form covers both halves only
   const CgFuse none{};
 #define L_XF(A, B)                                                                                     \
@@ -854,7 +885,7 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   *nparts = (int)grid.x;
   const dim3 block(6 * R * cfg.N2);
-  const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
+  const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * N);
 #define L_CGI(A, B)                                                                                  \
   if (insts)                                                                                         \
     hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true, true>), grid, block, lds, s, g, t,     \
@@ -879,7 +910,7 @@ hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg,
   const dim3 grid((unsigned)((rows + R - 1) / R), 1, (unsigned)ninst);
   *nparts = (int)grid.x;
   const dim3 block(6 * R * cfg.N2);
-  const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * (N + 1));
+  const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * N);
 #define L_CGL(A, B)                                                                                  \
   if (insts)                                                                                         \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, true>), grid, block, lds, s, g, t, fld,  \

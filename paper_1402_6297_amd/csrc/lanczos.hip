@@ -37,6 +37,7 @@ struct Run {
   std::vector<double2> H;
   int nb = 0;
   std::vector<double> theta, eta;
+  double start_h2 = 0;  // |h|^2 of the projected CG start of the current step
   std::vector<double2> Sk;
   nsf_stats st{};
   bool finished = false, converged = false;
@@ -208,11 +209,30 @@ int cg_graph_ready(CgGraph& cg, std::vector<Group>& groups, std::vector<Run*>& a
 }
 
 // w = A_r^{-1} bv by CG for every unfinished run, all advancing together.
+//
+// With the projected start (the default) each run solves instead for the part
+// of w that is A_r-orthogonal to the basis: the A_r-Galerkin solution in
+// span(V) is V h with h = V^* A_r w = V^* B_r v, the H column already formed
+// for the last basis vector v, so CG starts from r = bv - (A_r V) h and leaves
+// e = w - V h in w.  The stopping test stays ||b - A_r (V h + e)|| <= rtol ||b||.
+// The Gram-Schmidt pass that follows removes only what CG left in span(V),
+// and the Lanczos direction is the same vector as from the plain start.
 int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, CgGraph* cgg) {
   for (Run* r : act) {
     nsf_plan p = r->p;
+    int m = 0;
+    r->start_h2 = 0;
+    if (p->opt_cg_start && r->nb > 0 && r->nb <= 512) {
+      m = r->nb;
+      double2* hc = p->h_res + 64;
+      for (int i = 0; i < m; ++i) {
+        hc[i] = r->Hat(i, m - 1);
+        r->start_h2 += hc[i].x * hc[i].x + hc[i].y * hc[i].y;
+      }
+      NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * m, hipMemcpyHostToDevice, s));
+    }
     NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, p->d_cg + r->len, r->len, p->d_partial, p->d_state,
-                              r->cg_rtol, 5000, s));
+                              r->cg_rtol, 5000, s, m ? r->AV : nullptr, r->len, m, m ? p->d_coef : nullptr));
   }
   bool graph = cgg != nullptr;
   for (Run* r : act) graph = graph && r->p->opt_cg_graph;
@@ -274,8 +294,7 @@ int ortho_pass(Run* r) {
   nsf_plan p = r->p;
   hipStream_t s = p->stream;
   NSF_HIP(p, launch_multi_dot(r->AV, r->len, r->nb, r->w, r->len, p->d_partial, p->d_coef, s));
-  NSF_HIP(p, launch_multi_axpy(r->V, r->len, r->nb, p->d_coef, r->w, r->len, s));
-  NSF_HIP(p, launch_multi_axpy(r->AV, r->len, r->nb, p->d_coef, r->z, r->len, s));
+  NSF_HIP(p, launch_multi_axpy(r->V, r->len, r->nb, p->d_coef, r->w, r->len, s, r->AV, r->z));
   r->st.ortho_passes += 1;
   return dot_async(p, r->w, r->z, r->len, 1);
 }
@@ -477,7 +496,8 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
     if (again) NSF_HIP(act[0]->p, hipStreamSynchronize(s));
     for (size_t i = 0; i < act.size(); ++i) {
       Run* r = act[i];
-      if (!(r->p->h_res[1].x > 1e-20 * r->p->h_res[0].x)) {
+      // invariant subspace: nothing of A_r^{-1} B_r v is left outside span(V)
+      if (!(r->p->h_res[1].x > 1e-20 * (r->p->h_res[0].x + r->start_h2))) {
         if ((rc = refresh_direction(r, s))) return fail(rc);
       }
       if ((rc = admit_enqueue(r, r->nb, r->p->h_res[1].x))) return fail(rc);

@@ -205,8 +205,12 @@ hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipS
 // partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
 hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,
                                double2* partial, const int* skip, hipStream_t s);
+// x = 0 and r = p = b - sum_{i<m} c_i AV_i (c on device, m <= 512; plain r = b
+// when m = 0); the stopping threshold stays relative to ||b||.
 hipError_t launch_cg_init(const double2* b, double2* x, double2* r, double2* p, long long len,
-                          double2* partial, CgState* st, double rtol, int maxit, hipStream_t s);
+                          double2* partial, CgState* st, double rtol, int maxit, hipStream_t s,
+                          const double2* AV = nullptr, long long ld = 0, int m = 0,
+                          const double2* c = nullptr);
 hipError_t launch_cg_alpha(const double2* partial, int nparts, CgState* st, hipStream_t s);
 hipError_t launch_cg_update(double2* x, double2* r, const double2* p, const double2* q,
                             long long len, double2* partial, CgState* st, hipStream_t s);
@@ -219,9 +223,10 @@ hipError_t launch_cg_p(double2* p, const double2* r, long long len, CgState* st,
 // c[i] = sum_e conj(V_i[e]) w[e], i < m, written as m complex values to out.
 hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2* w, long long len,
                             double2* partial, double2* out, hipStream_t s);
-// w -= sum_i c[i] V_i  (c on device, m complex)
+// w -= sum_i c[i] V_i and, if V2 is given, z -= sum_i c[i] V2_i  (c on device, m <= 512)
 hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
-                             long long len, hipStream_t s);
+                             long long len, hipStream_t s, const double2* V2 = nullptr,
+                             double2* z = nullptr);
 // V[:, 0:k] = V[:, 0:m] S (S device, m x k column-major complex), in place.
 hipError_t launch_rotate(double2* V, long long ld, int m, int k, const double2* S, long long len,
                          hipStream_t s);
@@ -290,6 +295,7 @@ struct nsf_plan_s {
   int opt_fft_path = 0;     // 0 auto, 1 generic LDS-staged, 2 two-level without single-wave
   int opt_mid_cols = 16;    // pencils per workgroup of the fused z pass
   int opt_cg_graph = 1;     // CG iterations of the eigensolver replayed from a HIP graph
+  int opt_cg_start = 1;     // eigensolver CG starts from the Galerkin solution in span(V)
 
   std::string last_error;
 };

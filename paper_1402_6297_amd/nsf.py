@@ -34,6 +34,7 @@ NSF_OPT_CG_GRAPH = 3
 NSF_OPT_X_ROWS = 4
 NSF_OPT_YZ_COLS = 5
 NSF_OPT_MID_PAIRS = 6
+NSF_OPT_CG_START = 7
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",

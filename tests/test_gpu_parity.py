@@ -472,3 +472,25 @@ def test_batch_autotune_one_per_shape():
         assert B.autotune(reps=2) == 2
         st, om, res, stats, _ = B.eigs(4, res_tol=1e-9, cg_rtol=1e-11)
     assert st == nsf.NSF_OK and res.max() <= 1e-9
+
+
+@pytest.mark.parametrize("batched", [False, True], ids=["single", "batch"])
+def test_projected_cg_start_same_eigenpairs(batched):
+    """Starting each inner CG from the Galerkin solution in span(V) changes the
+    Lanczos directions only within the CG tolerance: same eigenvalues (1e-10),
+    both runs converged, fewer CG iterations in all."""
+    grids = [(16, 16, 16), (16, 16, 16), (8, 8, 8)] if batched else [(16, 16, 16)]
+    ks = [(0.1, 0.2, 0.3), (0.3, 0.1, 0.2), (0.2, 0.2, 0.1)][:len(grids)]
+    out = []
+    for start in (0, 1):
+        with nsf.Batch(grids, ks) as B:
+            for i, g in enumerate(grids):
+                B.set_chiral(i, *media.sphere_chiral(*g))
+                nsf.nsf_plan_set_option(B.plan(i), nsf.NSF_OPT_CG_START, start)
+            st, om, res, stats, _ = B.eigs(6, res_tol=1e-9, cg_rtol=1e-11, seed=2)
+            out.append((st, om, res, sum(s["cg_iters_total"] for s in stats)))
+    (s0, om0, r0, it0), (s1, om1, r1, it1) = out
+    assert s0 == s1 == nsf.NSF_OK
+    assert r0.max() <= 1e-9 and r1.max() <= 1e-9
+    assert np.abs(om1 - om0).max() <= 1e-10 * om0.max()
+    assert it1 < it0
