@@ -222,11 +222,14 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_check(const double* part, i
 
 // After the last pass: alpha = |r|^2 / p^*A p and beta = |r - alpha q|^2 / |r|^2,
 // the new residual norm expanded as |r|^2 - 2 alpha Re r^*q + alpha^2 |q|^2.
+// With np_mid > 0, p^*A p comes from the fused z pass's partials instead.
 __global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, int nparts, CgState* st,
-                                                          const InstDesc* insts) {
+                                                          const InstDesc* insts, const double* part_mid,
+                                                          int np_mid) {
   if (insts) {
     part = insts[blockIdx.x].cg.part_out;
     st = insts[blockIdx.x].cg.st;
+    part_mid = insts[blockIdx.x].cg.part_mid;
   }
   if (st->done) return;
   double2 a = make_double2(0, 0), b = make_double2(0, 0);
@@ -234,6 +237,10 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, in
     a.x += part[3 * i];
     a.y += part[3 * i + 1];
     b.x += part[3 * i + 2];
+  }
+  if (np_mid > 0) {
+    a.x = 0.0;
+    for (int i = threadIdx.x; i < np_mid; i += kRedThreads) a.x += part_mid[i];
   }
   a = block_sum(a);
   b = block_sum(b);
@@ -478,8 +485,9 @@ hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipS
 }
 
 hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s,
-                           const InstDesc* insts, int ninst) {
-  hipLaunchKernelGGL(k_cgf_step, dim3(ninst), dim3(kRedThreads), 0, s, part_out, nparts, st, insts);
+                           const InstDesc* insts, int ninst, const double* part_mid, int np_mid) {
+  hipLaunchKernelGGL(k_cgf_step, dim3(ninst), dim3(kRedThreads), 0, s, part_out, nparts, st, insts, part_mid,
+                     np_mid);
   return hipGetLastError();
 }
 

@@ -223,16 +223,17 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
 // transform over k2 in registers, the twiddle w^-(k1 m2), one LDS exchange, and
 // a radix-N1 transform over k1 that yields the outputs m2 + N2 m1 at exactly the
 // addresses the thread loaded.
-template <int N1, int N2, bool BT = false>
+template <int N1, int N2, bool BT = false, bool PQ = false>
 __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView med,
                                                  double2* __restrict__ fld, int P, const int* skip,
-                                                 const InstDesc* __restrict__ insts) {
+                                                 const InstDesc* __restrict__ insts, double* part_mid) {
   if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
     med = d.med;
     fld = d.fld;
     skip = d.skip;
+    part_mid = d.cg.part_mid;
   }
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
   }
   __syncthreads();
   const double inv_n = 1.0 / (double)n;
+  double pq[1] = {0.0};  // Re f^* (M f) / n: this thread's share of p^* A_r p
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const int k1 = n2 + d * N2;
@@ -326,8 +328,13 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
         const double2 own = out[d][k2];
         out[d][k2] = (h == 0) ? cscale(csub(cscale(own, eps), cmuli(cscale(other, gm))), sc)
                               : cscale(cadd(cmuli(cscale(other, gm)), own), sc);
+        if (PQ) pq[0] += own.x * out[d][k2].x + own.y * out[d][k2].y;
       }
     }
+  }
+  if (PQ) {
+    block_sum_k<1>(pq);  // synchronises the workgroup
+    if (threadIdx.x == 0) part_mid[blockIdx.x] = pq[0];
   }
   __syncthreads();  // partner values read before the tile is reused
   // forward z: radix N2 over k2, twiddle, exchange, radix N1 over k1
@@ -358,7 +365,9 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
 // XOR swizzle of the 16-element (256-byte) bank groups, chosen per split N1 x N2
 // so that the 16-lane groups of the strided second-radix reads, the first-radix
 // accesses and the synthesis / projection sweeps hit distinct 16-byte slots
-// (found by enumerating (s, a, b) against those access patterns).
+// (found by enumerating (s, a, b) against those access patterns).  Measured, the
+// swizzle pays in the forward projection pass and not in the inverse synthesis
+// pass (whose index arithmetic it lengthens), so only the former uses it.
 template <int N1, int N2>
 struct XSwz {
   static constexpr int s = 3, a = 0, b = 0;
@@ -370,10 +379,10 @@ template <> struct XSwz<16, 6> { static constexpr int s = 5, a = 9, b = 7; };
 template <> struct XSwz<16, 3> { static constexpr int s = 3, a = 0, b = 12; };
 template <> struct XSwz<8, 4> { static constexpr int s = 3, a = 0, b = 5; };
 template <> struct XSwz<4, 4> { static constexpr int s = 3, a = 0, b = 5; };
-template <int N1, int N2>
+template <int N1, int N2, bool SW>
 __device__ __forceinline__ int xpos(int e, int r) {
   using W = XSwz<N1, N2>;
-  return e ^ ((((e >> W::s) * W::a) + r * W::b) & 15);
+  return SW ? e ^ ((((e >> W::s) * W::a) + r * W::b) & 15) : e;
 }
 
 // R rows per workgroup; LDS tile[(c * R + r) * N + xpos(e, r)].
@@ -454,7 +463,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
       const double2 ya = CG ? yv[0] : y[f], yb = CG ? yv[1] : y[n + f];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
-        tile[(cc * R + r) * NP + xpos<N1, N2>(i1, r)] = csub(cmulc(B.pi1[cc], yb), cmulc(B.pi2[cc], ya));
+        tile[(cc * R + r) * NP + xpos<N1, N2, false>(i1, r)] = csub(cmulc(B.pi1[cc], yb), cmulc(B.pi2[cc], ya));
     }
     if (PART == kPartBoth || PART == kPartQ) {
       const long long o = (PART == kPartBoth) ? 2 * n : 0;
@@ -462,7 +471,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
       const double2 yc = CG ? yv[2] : y[o + f], yd = CG ? yv[3] : y[o + n + f];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
-        tile[((cb + cc) * R + r) * NP + xpos<N1, N2>(i1, r)] = cadd(cmul(B.pi1[cc], yc), cmul(B.pi2[cc], yd));
+        tile[((cb + cc) * R + r) * NP + xpos<N1, N2, false>(i1, r)] = cadd(cmul(B.pi1[cc], yc), cmul(B.pi2[cc], yd));
     }
   };
   // this thread's slots are e = threadIdx.x + it * blockDim.x (blockDim = F R N2
@@ -491,13 +500,13 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   double2 v[N1];
   if (active) {
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[xpos<N1, N2>(n2 + N2 * n1, r)];
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[xpos<N1, N2, false>(n2 + N2 * n1, r)];
     step1<N1, N2, +1>(v, n2, twl);
   }
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) T[xpos<N1, N2>(n2 + N2 * k1, r)] = v[k1];
+    for (int k1 = 0; k1 < N1; ++k1) T[xpos<N1, N2, false>(n2 + N2 * k1, r)] = v[k1];
   }
   __syncthreads();
   if (!active) return;
@@ -508,7 +517,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
     if (k1 < N1) {
       double2 u[N2];
 #pragma unroll
-      for (int m = 0; m < N2; ++m) u[m] = T[xpos<N1, N2>(m + N2 * k1, r)];
+      for (int m = 0; m < N2; ++m) u[m] = T[xpos<N1, N2, false>(m + N2 * k1, r)];
       reg_dft<N2, +1>(u);
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) out[k1 + N1 * k2] = u[k2];
@@ -516,7 +525,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   }
 }
 
-template <int N1, int N2, int PART, bool CG = false, bool BT = false>
+template <int N1, int N2, int PART, bool CG = false, bool BT = false, bool NOPQ = false>
 __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
                                                      double2* __restrict__ out, int R,
                                                      const int* skip, CgFuse cg,
@@ -556,7 +565,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
   if (active) {
     step1<N1, N2, -1>(v, n2, twl);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) T[xpos<N1, N2>(n2 + N2 * k1, r)] = v[k1];
+    for (int k1 = 0; k1 < N1; ++k1) T[xpos<N1, N2, true>(n2 + N2 * k1, r)] = v[k1];
   }
   __syncthreads();
   double2 res[D][N2];
@@ -566,7 +575,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       const int k1 = n2 + d * N2;
       if (k1 < N1) {
 #pragma unroll
-        for (int m = 0; m < N2; ++m) res[d][m] = T[xpos<N1, N2>(m + N2 * k1, r)];
+        for (int m = 0; m < N2; ++m) res[d][m] = T[xpos<N1, N2, true>(m + N2 * k1, r)];
         reg_dft<N2, -1>(res[d]);
       }
     }
@@ -578,7 +587,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       const int k1 = n2 + d * N2;
       if (k1 < N1) {
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) T[xpos<N1, N2>(k1 + N1 * k2, r)] = res[d][k2];
+        for (int k2 = 0; k2 < N2; ++k2) T[xpos<N1, N2, true>(k1 + N1 * k2, r)] = res[d][k2];
       }
     }
   }
@@ -599,7 +608,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
     if (CG) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        pv[b] = cg.p[b * n + f];
+        if (!NOPQ) pv[b] = cg.p[b * n + f];
         rv[b] = cg.r[b * n + f];
       }
     }
@@ -609,7 +618,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
     if (PART == kPartBoth || PART == kPartP) {
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
-        const double2 o = tile[(cc * R + rr) * NP + xpos<N1, N2>(i1, rr)];
+        const double2 o = tile[(cc * R + rr) * NP + xpos<N1, N2, true>(i1, rr)];
         oa = csub(oa, cmul(B.pi2[cc], o));
         ob = cadd(ob, cmul(B.pi1[cc], o));
       }
@@ -622,7 +631,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       double2 oc = make_double2(0, 0), od = make_double2(0, 0);
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
-        const double2 o = tile[((cb + cc) * R + rr) * NP + xpos<N1, N2>(i1, rr)];
+        const double2 o = tile[((cb + cc) * R + rr) * NP + xpos<N1, N2, true>(i1, rr)];
         oc = cadd(oc, cmulc(B.pi1[cc], o));
         od = cadd(od, cmulc(B.pi2[cc], o));
       }
@@ -632,7 +641,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
         const double2 qv[4] = {oa, ob, oc, od};
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          acc[0] += pv[b].x * qv[b].x + pv[b].y * qv[b].y;
+          if (!NOPQ) acc[0] += pv[b].x * qv[b].x + pv[b].y * qv[b].y;
           acc[1] += cabs2(qv[b]);
           acc[2] += rv[b].x * qv[b].x + rv[b].y * qv[b].y;
         }
@@ -746,32 +755,53 @@ hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int
 
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
                              int P_want, const int* skip, hipStream_t s, const InstDesc* insts,
-                             int ninst) {
+                             int ninst, double* part_mid, int* np_mid) {
   const int N = g.n3;
+  if (np_mid) *np_mid = 0;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
   if (g.mid_pairs) {
+    const size_t lmax = lds_limit() - 1024;  // room for the kernel's static LDS (reductions)
     int P = pick_cols(g.n1, P_want);
-    while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lds_limit())) P /= 2;
-    if (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lds_limit()) return hipErrorInvalidValue;
+    while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax)) P /= 2;
+    if (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax) return hipErrorInvalidValue;
     const unsigned items = (unsigned)(3 * (g.n1 / P) * g.n2);
     const dim3 block(2 * P * cfg.N2);
     const size_t lds = sizeof(double2) * (size_t)(N + 2 * N * P);
     const dim3 grid(items, 1, (unsigned)ninst);
+    const bool pq = np_mid && (insts || part_mid) && items <= 2u * kMidSlots;
+    if (pq) *np_mid = (int)items;
 #define L_PAIR(A, B)                                                                                 \
   if (lds > 65536) { /* opt in once per kernel, to the device limit (not a stream operation) */     \
-    static const hipError_t e0 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fz_pair<A, B>), \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit());  \
-    static const hipError_t e1 = hipFuncSetAttribute(                                                \
-        reinterpret_cast<const void*>(&k_fz_pair<A, B, true>),                                       \
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit());                               \
+    const void* ks[4] = {reinterpret_cast<const void*>(&k_fz_pair<A, B, false, false>),              \
+                         reinterpret_cast<const void*>(&k_fz_pair<A, B, true, false>),               \
+                         reinterpret_cast<const void*>(&k_fz_pair<A, B, false, true>),               \
+                         reinterpret_cast<const void*>(&k_fz_pair<A, B, true, true>)};              \
+    static const hipError_t e0 = [&]() { /* dynamic LDS up to the limit less the static part */    \
+      for (const void* k : ks) {                                                                     \
+        hipFuncAttributes fa;                                                                        \
+        hipError_t e = hipFuncGetAttributes(&fa, k);                                                 \
+        if (e == hipSuccess)                                                                         \
+          e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,                     \
+                                  (int)(lds_limit() - fa.sharedSizeBytes));                          \
+        if (e != hipSuccess) return e;                                                               \
+      }                                                                                              \
+      return hipSuccess;                                                                             \
+    }();                                                                                             \
     if (e0 != hipSuccess) return e0;                                                                 \
-    if (e1 != hipSuccess) return e1;                                                                 \
   }                                                                                                  \
-  if (insts)                                                                                         \
-    hipLaunchKernelGGL((k_fz_pair<A, B, true>), grid, block, lds, s, g, t, med, fld, P, skip, insts); \
+  if (insts && pq)                                                                                   \
+    hipLaunchKernelGGL((k_fz_pair<A, B, true, true>), grid, block, lds, s, g, t, med, fld, P, skip,  \
+                       insts, part_mid);                                                             \
+  else if (insts)                                                                                    \
+    hipLaunchKernelGGL((k_fz_pair<A, B, true>), grid, block, lds, s, g, t, med, fld, P, skip, insts, \
+                       part_mid);                                                                    \
+  else if (pq)                                                                                       \
+    hipLaunchKernelGGL((k_fz_pair<A, B, false, true>), grid, block, lds, s, g, t, med, fld, P, skip, \
+                       insts, part_mid);                                                             \
   else                                                                                               \
-    hipLaunchKernelGGL((k_fz_pair<A, B>), grid, block, lds, s, g, t, med, fld, P, skip, insts);
+    hipLaunchKernelGGL((k_fz_pair<A, B>), grid, block, lds, s, g, t, med, fld, P, skip, insts,       \
+                       part_mid);
     NSF_FAST_SWITCH(N, L_PAIR)
 #undef L_PAIR
     return hipGetLastError();
@@ -900,7 +930,7 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
 
 hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
                                const int* skip, int* nparts, hipStream_t s, const InstDesc* insts,
-                               int ninst) {
+                               int ninst, bool pq_done) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -912,9 +942,15 @@ hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg,
   const dim3 block(6 * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * N);
 #define L_CGL(A, B)                                                                                  \
-  if (insts)                                                                                         \
+  if (insts && pq_done)                                                                              \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, true, true>), grid, block, lds, s, g, t,  \
+                       fld, cg.q, R, skip, cg, insts);                                               \
+  else if (insts)                                                                                    \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, true>), grid, block, lds, s, g, t, fld,  \
                        cg.q, R, skip, cg, insts);                                                    \
+  else if (pq_done)                                                                                  \
+    hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, false, true>), grid, block, lds, s, g, t, \
+                       fld, cg.q, R, skip, cg, insts);                                               \
   else                                                                                               \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true>), grid, block, lds, s, g, t, fld, cg.q, \
                        R, skip, cg, insts);

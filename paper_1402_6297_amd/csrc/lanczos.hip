@@ -135,14 +135,15 @@ int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
     const Geom& g = p0->geom;
     const InstDesc* d = G.d_desc;
     const CgFuse none{};
-    int np1 = 0, np5 = 0;
+    int np1 = 0, np5 = 0, npm = 0;
     NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na));
     NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na,
+                                  nullptr, &npm));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na));
-    NSF_HIP(p0, launch_cgf_step(nullptr, np5, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, npm > 0));
+    NSF_HIP(p0, launch_cgf_step(nullptr, np5, nullptr, s, d, na, nullptr, npm));
   }
   return NSF_OK;
 }

@@ -115,9 +115,14 @@ hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, con
 hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int nf, double2* fld,
                           int post_twist, int pre_twist, const int* skip, hipStream_t s,
                           const struct InstDesc* insts = nullptr, int ninst = 1);
+// With np_mid given and the field-pair kernel in use, also writes per-workgroup
+// partials of Re p^* A_r p (the fields' real-space quadratic form) to part_mid
+// (batched: to each descriptor's cg.part_mid) and sets *np_mid to their count;
+// otherwise *np_mid = 0.
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
                              int P_want, const int* skip, hipStream_t s,
-                             const struct InstDesc* insts = nullptr, int ninst = 1);
+                             const struct InstDesc* insts = nullptr, int ninst = 1,
+                             double* part_mid = nullptr, int* np_mid = nullptr);
 hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld,
                                   double2* out, const int* skip, hipStream_t s,
                                   const struct InstDesc* insts = nullptr, int ninst = 1);
@@ -142,6 +147,7 @@ constexpr int kRedBlocks = 1024;       // partial-sum slots for one reduction
 constexpr int kPartialSlots = 131072;  // partial-sum slots of the multi-vector dot (512 x 256)
 constexpr int kCoefSlots = 1024;       // device coefficient vector of the Lanczos steps
 constexpr int kResSlots = 1100;        // reduction results (and host copies of coefficients)
+constexpr int kMidSlots = 32768;       // doubles x 2: partials of the fused z pass
 
 struct CgState {
   double rr;        // r^* r of the current iterate
@@ -164,6 +170,7 @@ struct CgFuse {
   CgState* st;
   double* part_in;   // per-workgroup |r|^2 of the first pass
   double* part_out;  // per-workgroup (Re p^*q, |q|^2, Re r^*q) of the last pass
+  double* part_mid;  // per-workgroup Re p^* A_r p of the fused z pass (field pairs)
 };
 
 // Per-instance pointers of a batched launch (instances of one grid shape):
@@ -190,9 +197,10 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
                                 const InstDesc* insts = nullptr, int ninst = 1);
 // Last pass: q = projection of the forward x transform (written to cg.q) and
 // the per-workgroup partial sums of p^*q, |q|^2, r^*q.
+// pq_done: the fused z pass already produced p^* A_r p, so p is not read here.
 hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
                                const int* skip, int* nparts, hipStream_t s,
-                               const InstDesc* insts = nullptr, int ninst = 1);
+                               const InstDesc* insts = nullptr, int ninst = 1, bool pq_done = false);
 // Scalar steps of the fused CG: check |r|^2 after the first pass, then alpha,
 // beta from the last pass (|r - alpha q|^2 by expansion).
 // Batched forms (insts != nullptr): one workgroup per instance, partials and
@@ -200,7 +208,8 @@ hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg,
 hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipStream_t s,
                             const InstDesc* insts = nullptr, int ninst = 1);
 hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s,
-                           const InstDesc* insts = nullptr, int ninst = 1);
+                           const InstDesc* insts = nullptr, int ninst = 1,
+                           const double* part_mid = nullptr, int np_mid = 0);
 
 // partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
 hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,
@@ -318,7 +327,8 @@ int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip);
 hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, const int* skip);
 hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post_twist, int pre_twist,
                    const int* skip);
-hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip);
+hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid = nullptr,
+                      int* np_mid = nullptr);
 hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip);
 int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
                  double* relres, long long* matvecs);

@@ -65,7 +65,8 @@ int ensure_device(nsf_plan p) {
   p->tabs.twist = p->d_tables + ntab;
   p->tabs.tw = p->d_tables + 2 * ntab;
   NSF_HIP(p, hipMalloc(&p->d_fields, sizeof(double2) * 6 * (size_t)g.n));
-  NSF_HIP(p, hipMalloc(&p->d_partial, sizeof(double2) * (size_t)(kPartialSlots + kCoefSlots + kResSlots)));
+  NSF_HIP(p, hipMalloc(&p->d_partial,
+                       sizeof(double2) * (size_t)(kPartialSlots + kCoefSlots + kResSlots + kMidSlots)));
   p->d_coef = p->d_partial + kPartialSlots;
   p->d_res = p->d_coef + kCoefSlots;
   NSF_HIP(p, hipHostMalloc(&p->h_res, sizeof(double2) * kResSlots));
@@ -105,12 +106,14 @@ hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post
   return launch_yz_pass(g, p->ax[axis], p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
 }
 
-hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip) {
+hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid, int* np_mid) {
   const Geom& g = p->geom;
+  if (np_mid) *np_mid = 0;
   if (p->opt_fft_path == 2 && wave_mid_ok(g))
     return launch_wave_z_mid(g, p->tabs, medium_view(p), fld, skip, p->stream);
   if (p->opt_fft_path != 1 && fast_axis(g.n3))
-    return launch_fast_z_mid(g, p->tabs, medium_view(p), fld, p->opt_mid_cols, skip, p->stream);
+    return launch_fast_z_mid(g, p->tabs, medium_view(p), fld, p->opt_mid_cols, skip, p->stream, nullptr, 1,
+                             part_mid, np_mid);
   return launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), fld, skip, p->stream);
 }
 

@@ -65,7 +65,8 @@ bool cg_fusable(nsf_plan p) {
 CgFuse cg_fuse_of(nsf_plan p, double2* x) {
   const long long len = 4 * p->geom.n;
   return CgFuse{x, p->d_cg, p->d_cg + len, p->d_cg + 2 * len, p->d_state,
-                reinterpret_cast<double*>(p->d_partial), reinterpret_cast<double*>(p->d_partial) + 65536};
+                reinterpret_cast<double*>(p->d_partial), reinterpret_cast<double*>(p->d_partial) + 65536,
+                reinterpret_cast<double*>(p->d_partial + kPartialSlots + kCoefSlots + kResSlots)};
 }
 
 // One CG iteration of plan p, enqueued (every kernel returns at once when the
@@ -85,10 +86,11 @@ int cg_iteration(nsf_plan p, double2* x, bool fused) {
     NSF_HIP(p, launch_fast_cg_first(p->geom, p->tabs, cgf, p->d_fields, skip, &np1, s));
     NSF_HIP(p, launch_cgf_check(cgf.part_in, np1, st, s));
     NSF_HIP(p, pass_yz(p, 1, +1, 6, p->d_fields, 0, 0, skip));
-    NSF_HIP(p, pass_z_mid(p, p->d_fields, skip));
+    int npm = 0;
+    NSF_HIP(p, pass_z_mid(p, p->d_fields, skip, cgf.part_mid, &npm));
     NSF_HIP(p, pass_yz(p, 1, -1, 6, p->d_fields, 0, 0, skip));
-    NSF_HIP(p, launch_fast_cg_last(p->geom, p->tabs, cgf, p->d_fields, skip, &np5, s));
-    NSF_HIP(p, launch_cgf_step(cgf.part_out, np5, st, s));
+    NSF_HIP(p, launch_fast_cg_last(p->geom, p->tabs, cgf, p->d_fields, skip, &np5, s, nullptr, 1, npm > 0));
+    NSF_HIP(p, launch_cgf_step(cgf.part_out, np5, st, s, nullptr, 1, cgf.part_mid, npm));
     return NSF_OK;
   }
   const int nparts = reduce_parts_for(len);

@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnsf.so")
+# NSF_LIB names another build of the same library (for A/B timing of builds)
+LIB_PATH = os.environ.get("NSF_LIB") or os.path.join(_HERE, "libnsf.so")
 
 NSF_OK = 0
 NSF_NOT_CONVERGED = 1
