@@ -38,10 +38,35 @@ __device__ inline double2 block_sum(double2 v) {
   return s;
 }
 
+// Four independent accumulators per thread, so four loads are in flight at once
+// (the fold is latency-bound otherwise); fixed order, hence reproducible.
 __device__ inline double2 fold_partials(const double2* partial, int nparts) {
-  double2 v = make_double2(0, 0);
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v = cadd(v, partial[i]);
-  return block_sum(v);
+  double2 v0 = make_double2(0, 0), v1 = v0, v2 = v0, v3 = v0;
+  const int bd = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 3 * bd < nparts; i += 4 * bd) {
+    v0 = cadd(v0, partial[i]);
+    v1 = cadd(v1, partial[i + bd]);
+    v2 = cadd(v2, partial[i + 2 * bd]);
+    v3 = cadd(v3, partial[i + 3 * bd]);
+  }
+  for (; i < nparts; i += bd) v0 = cadd(v0, partial[i]);
+  return block_sum(cadd(cadd(v0, v1), cadd(v2, v3)));
+}
+
+// sum of part[0..n) (strided by `stride` doubles from `part`), four accumulators per thread
+__device__ inline double fold_doubles(const double* part, int n, int stride) {
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  const int bd = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 3 * bd < n; i += 4 * bd) {
+    a0 += part[(long long)i * stride];
+    a1 += part[(long long)(i + bd) * stride];
+    a2 += part[(long long)(i + 2 * bd) * stride];
+    a3 += part[(long long)(i + 3 * bd) * stride];
+  }
+  for (; i < n; i += bd) a0 += part[(long long)i * stride];
+  return (a0 + a1) + (a2 + a3);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_dot(const double2* __restrict__ x,
@@ -63,8 +88,9 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double2* partial, 
 }
 
 // ------------------------------------------------------------------ CG
-// x = 0, r = p = b - sum_i c_i AV_i (the residual of the start x0 = sum_i c_i V_i
-// when AV_i = A V_i; no sum when m = 0); partials of (|b|^2, |r|^2).
+// x = 0, r = p = b - sum_j c_j AV_{idx_j} (the residual of the start
+// x0 = sum_j c_j V_{idx_j} when AV_i = A V_i; no sum when m = 0); partials of
+// (|b|^2, |r|^2).  c holds m coefficients followed by the m indices (in .x).
 __global__ __launch_bounds__(kRedThreads) void k_cg_init(const double2* __restrict__ b,
                                                          double2* __restrict__ x,
                                                          double2* __restrict__ r,
@@ -73,15 +99,19 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_init(const double2* __restri
                                                          const double2* __restrict__ AV, long long ld,
                                                          int m, const double2* __restrict__ c) {
   __shared__ double2 cs[512];
-  for (int i = threadIdx.x; i < m; i += kRedThreads) cs[i] = c[i];
+  __shared__ int ix[512];
+  for (int i = threadIdx.x; i < m; i += kRedThreads) {
+    cs[i] = c[i];
+    ix[i] = (int)c[m + i].x;
+  }
   __syncthreads();
   double2 acc = make_double2(0, 0);
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < len;
        i += (long long)gridDim.x * kRedThreads) {
     const double2 v = b[i];
     double2 rv = v;
-#pragma unroll 8
-    for (int j = 0; j < m; ++j) rv = csub(rv, cmul(cs[j], AV[j * ld + i]));
+#pragma unroll 4
+    for (int j = 0; j < m; ++j) rv = csub(rv, cmul(cs[j], AV[ix[j] * ld + i]));
     x[i] = make_double2(0, 0);
     r[i] = rv;
     p[i] = rv;
@@ -201,8 +231,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_check(const double* part, i
     st = insts[blockIdx.x].cg.st;
   }
   if (st->done || st->iter == 0) return;
-  double2 v = make_double2(0, 0);
-  for (int i = threadIdx.x; i < nparts; i += kRedThreads) v.x += part[i];
+  double2 v = make_double2(fold_doubles(part, nparts, 1), 0);
   v = block_sum(v);
   if (threadIdx.x == 0) {
     const double rr = v.x;
@@ -232,16 +261,10 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, in
     part_mid = insts[blockIdx.x].cg.part_mid;
   }
   if (st->done) return;
-  double2 a = make_double2(0, 0), b = make_double2(0, 0);
-  for (int i = threadIdx.x; i < nparts; i += kRedThreads) {
-    a.x += part[3 * i];
-    a.y += part[3 * i + 1];
-    b.x += part[3 * i + 2];
-  }
-  if (np_mid > 0) {
-    a.x = 0.0;
-    for (int i = threadIdx.x; i < np_mid; i += kRedThreads) a.x += part_mid[i];
-  }
+  double2 a, b;
+  a.x = np_mid > 0 ? fold_doubles(part_mid, np_mid, 1) : fold_doubles(part, nparts, 3);
+  a.y = fold_doubles(part + 1, nparts, 3);
+  b = make_double2(fold_doubles(part + 2, nparts, 3), 0);
   a = block_sum(a);
   b = block_sum(b);
   if (threadIdx.x == 0) {

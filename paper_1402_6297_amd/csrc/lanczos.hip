@@ -224,13 +224,26 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
     int m = 0;
     r->start_h2 = 0;
     if (p->opt_cg_start && r->nb > 0 && r->nb <= 512) {
-      m = r->nb;
-      double2* hc = p->h_res + 64;
-      for (int i = 0; i < m; ++i) {
-        hc[i] = r->Hat(i, m - 1);
-        r->start_h2 += hc[i].x * hc[i].x + hc[i].y * hc[i].y;
+      // h; entries below 1e-8 max|h| are left to the Gram-Schmidt pass (h is
+      // nearly tridiagonal between restarts, so this skips most of A_r V)
+      const int nb = r->nb;
+      double hmax = 0;
+      for (int i = 0; i < nb; ++i) {
+        const double2 h = r->Hat(i, nb - 1);
+        hmax = std::max(hmax, std::hypot(h.x, h.y));
+        r->start_h2 += h.x * h.x + h.y * h.y;
       }
-      NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * m, hipMemcpyHostToDevice, s));
+      double2* hc = p->h_res + 64;
+      for (int i = 0; i < nb; ++i) {
+        const double2 h = r->Hat(i, nb - 1);
+        if (std::hypot(h.x, h.y) > 1e-8 * hmax) {
+          hc[m] = h;
+          hc[512 + m] = make_double2((double)i, 0.0);
+          ++m;
+        }
+      }
+      for (int j = 0; j < m; ++j) hc[m + j] = hc[512 + j];
+      if (m) NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * 2 * m, hipMemcpyHostToDevice, s));
     }
     NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, p->d_cg + r->len, r->len, p->d_partial, p->d_state,
                               r->cg_rtol, 5000, s, m ? r->AV : nullptr, r->len, m, m ? p->d_coef : nullptr));

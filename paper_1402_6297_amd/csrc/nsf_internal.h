@@ -214,8 +214,9 @@ hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipS
 // partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
 hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,
                                double2* partial, const int* skip, hipStream_t s);
-// x = 0 and r = p = b - sum_{i<m} c_i AV_i (c on device, m <= 512; plain r = b
-// when m = 0); the stopping threshold stays relative to ||b||.
+// x = 0 and r = p = b - sum_{j<m} c_j AV_{idx_j} (c on device: m coefficients,
+// then the m indices as doubles in .x; m <= 512; plain r = b when m = 0); the
+// stopping threshold stays relative to ||b||.
 hipError_t launch_cg_init(const double2* b, double2* x, double2* r, double2* p, long long len,
                           double2* partial, CgState* st, double rtol, int maxit, hipStream_t s,
                           const double2* AV = nullptr, long long ld = 0, int m = 0,
