@@ -70,7 +70,7 @@ enum {
 };
 
 /* Medium kinds reported by nsf_plan_query. */
-enum { NSF_MEDIUM_NONE = 0, NSF_MEDIUM_CHIRAL = 1, NSF_MEDIUM_PSEUDOCHIRAL = 2 };
+enum { NSF_MEDIUM_NONE = 0, NSF_MEDIUM_CHIRAL = 1, NSF_MEDIUM_PSEUDOCHIRAL = 2, NSF_MEDIUM_GENERAL = 3 };
 
 /*
  * Create a plan for one Bloch vector on an n1 x n2 x n3 Yee grid of the simple
@@ -156,10 +156,10 @@ int nsf_plan_query(nsf_plan plan, long long* n, int* medium_kind,
 /*
  * Chiral medium (Sec. 4.3): eps_d = diag(eps), mu_d = I, xi_d = i diag(gamma),
  * zeta_d = -i diag(gamma), per voxel g (length n each, float64).  host or
- * device pointers (on_device = 0 / 1); device data is copied.  Validation of
- * host data (Sec. 4.1 assumption; Phi = eps - gamma^2 > 0, all finite) happens
- * before any device call: NSF_E_NOT_HHPD or NSF_E_ARG.  Device data is
- * validated by a kernel and the call synchronises the stream.
+ * device pointers (on_device = 0 / 1); the library keeps its own copy.  The
+ * values are validated on the host (device data is copied there first) against
+ * the Sec. 4.1 assumption: Phi = eps - gamma^2 > 0 and all finite, else
+ * NSF_E_NOT_HHPD or NSF_E_ARG naming the voxel.  Synchronises the stream.
  */
 int nsf_set_medium_chiral(nsf_plan plan, const double* eps, const double* gamma,
                           int on_device);
@@ -173,6 +173,22 @@ int nsf_set_medium_chiral(nsf_plan plan, const double* eps, const double* gamma,
 int nsf_set_medium_pseudochiral(nsf_plan plan, int axis_a, int axis_b,
                                 const double* eps, const double* gamma,
                                 int on_device);
+
+/*
+ * General medium (Sec. 3): per voxel g, 3 x 3 complex tensors eps_d, mu_d,
+ * xi_d, zeta_d, each n x 9 nsf_c128 (voxel-major, row-major 3 x 3), host or
+ * device pointers (on_device = 0 / 1; the library keeps its own data).  The
+ * HHPD assumption of Sec. 4.1 is checked per voxel on the host: all finite
+ * (NSF_E_ARG), eps and mu Hermitian, mu positive definite, zeta = xi^* and
+ * Phi = eps - xi mu^-1 zeta positive definite (to 1e-14 of the voxel's largest
+ * entry; NSF_E_NOT_HHPD naming the voxel).  The library stores, per voxel, the
+ * 6 x 6 Hermitian middle factor of A_r (Thm 4.2),
+ * [[mu^-1 zeta Phi^-1 xi mu^-1 + mu^-1, mu^-1 zeta Phi^-1], [Phi^-1 xi mu^-1, Phi^-1]]
+ * (21 complex values, 336 n bytes).  Its A_r passes use the six-field fused z
+ * pass, since such a medium can couple all six fields.  Synchronises.
+ */
+int nsf_set_medium_tensor(nsf_plan plan, const nsf_c128* eps, const nsf_c128* mu,
+                          const nsf_c128* xi, const nsf_c128* zeta, int on_device);
 
 /*
  * Basis applies (Thm 2.5; T by twisted FFT, Sec. 4.2).  All pointers device.

@@ -283,4 +283,39 @@ __device__ __forceinline__ void medium_apply(const MediumView& m, double2 eg, do
   }
 }
 
+// General (HHPD) media: [E; H] <- M [E; H] / n with M the voxel's 6 x 6
+// Hermitian middle factor [[mu^-1 zeta Phi^-1 xi mu^-1 + mu^-1, mu^-1 zeta Phi^-1],
+// [Phi^-1 xi mu^-1, Phi^-1]] (Thm 4.2), stored as its upper triangle.
+__device__ __forceinline__ void general_apply(const double2* __restrict__ Mu, double inv_n, double2* E,
+                                              double2* H) {
+  double2 v[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
+  double2 o[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) o[i] = make_double2(0, 0);
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int j = i; j < 6; ++j, ++k) {
+      const double2 m = Mu[k];
+      o[i] = cadd(o[i], cmul(m, v[j]));
+      if (j != i) o[j] = cadd(o[j], cmulc(m, v[i]));  // M_ji = conj(M_ij)
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    E[c] = cscale(o[c], inv_n);
+    H[c] = cscale(o[3 + c], inv_n);
+  }
+}
+
+// The constitutive step of voxel gi for any medium kind.
+__device__ __forceinline__ void medium_apply_at(const MediumView& m, long long gi, double inv_n, double2* E,
+                                                double2* H) {
+  if (m.kind == kMedGeneral)
+    general_apply(m.mg + gi * kGenEntries, inv_n, E, H);
+  else
+    medium_apply(m, m.eg[gi], inv_n, E, H);
+}
+
 }  // namespace nsf

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
       E[cc] = tile[(cc * N + j) * P + pp];
       H[cc] = tile[((3 + cc) * N + j) * P + pp];
     }
-    medium_apply(med, med.eg[base + j * stride + pp], inv_n, E, H);
+    medium_apply_at(med, base + j * stride + pp, inv_n, E, H);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       tile[(cc * N + j) * P + pp] = E[cc];
@@ -760,7 +760,7 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
   if (np_mid) *np_mid = 0;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
-  if (g.mid_pairs) {
+  if (g.mid_pairs && med.kind != kMedGeneral) {  // general media couple all six fields
     const size_t lmax = lds_limit() - 1024;  // room for the kernel's static LDS (reductions)
     int P = pick_cols(g.n1, P_want);
     while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax)) P /= 2;

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_z_mid(Geom g, AxisPlan ax, Tables 
       E[c] = tile[(c * N + j) * P + p];
       H[c] = tile[((3 + c) * N + j) * P + p];
     }
-    medium_apply(med, med.eg[gi], inv_n, E, H);
+    medium_apply_at(med, gi, inv_n, E, H);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       tile[(c * N + j) * P + p] = E[c];

@@ -59,12 +59,17 @@ struct Geom {
   int mid_pairs = 1; // fused z pass: 1 one field pair per workgroup, 0 all six fields
 };
 
-enum MediumKind { kMedNone = 0, kMedChiral = 1, kMedPseudo = 2 };
+enum MediumKind { kMedNone = 0, kMedChiral = 1, kMedPseudo = 2, kMedGeneral = 3 };
+
+// Entries of the general per-voxel middle factor kept per voxel: the upper
+// triangle of a 6 x 6 Hermitian matrix, row by row.
+constexpr int kGenEntries = 21;
 
 struct MediumView {
   int kind;
   int pa, pb, po;        // pseudochiral coupled axes and the third axis
   const double2* eg;     // per voxel (eps, gamma)
+  const double2* mg;     // general media: kGenEntries per voxel
 };
 
 // Which half of the synthesis / projection a pass performs.
@@ -282,6 +287,7 @@ struct nsf_plan_s {
   int medium_kind = nsf::kMedNone;
   int pa = 0, pb = 1, po = 2;
   double2* d_medium = nullptr;  // (eps, gamma) per voxel
+  double2* d_mgen = nullptr;    // general media: 6x6 middle factor per voxel (upper triangle)
 
   // workspace
   double2* d_fields = nullptr;  // 6 n

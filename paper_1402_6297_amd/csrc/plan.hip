@@ -4,6 +4,9 @@
 #include <cstring>
 #include <mutex>
 
+#include <complex>
+#include <string>
+
 #include "nsf_internal.h"
 
 namespace {
@@ -86,6 +89,7 @@ MediumView medium_view(nsf_plan p) {
   m.pb = p->pb;
   m.po = p->po;
   m.eg = p->d_medium;
+  m.mg = p->d_mgen;
   return m;
 }
 
@@ -109,7 +113,7 @@ hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post
 hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid, int* np_mid) {
   const Geom& g = p->geom;
   if (np_mid) *np_mid = 0;
-  if (p->opt_fft_path == 2 && wave_mid_ok(g))
+  if (p->opt_fft_path == 2 && wave_mid_ok(g) && p->medium_kind != kMedGeneral)
     return launch_wave_z_mid(g, p->tabs, medium_view(p), fld, skip, p->stream);
   if (p->opt_fft_path != 1 && fast_axis(g.n3))
     return launch_fast_z_mid(g, p->tabs, medium_view(p), fld, p->opt_mid_cols, skip, p->stream, nullptr, 1,
@@ -293,6 +297,7 @@ void nsf_plan_destroy(nsf_plan p) {
     hipHostFree(p->h_flags);
     hipHostFree(p->h_res);
     if (p->d_medium) hipFree(p->d_medium);
+    if (p->d_mgen) hipFree(p->d_mgen);
     if (p->d_cg) hipFree(p->d_cg);
     if (p->d_basis) hipFree(p->d_basis);
     if (p->d_small) hipFree(p->d_small);
@@ -401,9 +406,156 @@ int set_medium(nsf_plan p, int kind, int pa, int pb, const double* eps, const do
   return NSF_OK;
 }
 
+// ---- general media: 3 x 3 complex blocks per voxel
+typedef std::complex<double> cplx;
+struct M3 {
+  cplx a[3][3];
+};
+
+M3 load3(const double2* src) {
+  M3 m;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) m.a[i][j] = cplx(src[3 * i + j].x, src[3 * i + j].y);
+  return m;
+}
+M3 mul3(const M3& x, const M3& y) {
+  M3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cplx s = 0;
+      for (int k = 0; k < 3; ++k) s += x.a[i][k] * y.a[k][j];
+      r.a[i][j] = s;
+    }
+  return r;
+}
+M3 adj3(const M3& x) {
+  M3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) r.a[i][j] = std::conj(x.a[j][i]);
+  return r;
+}
+double absmax3(const M3& x) {
+  double s = 0;
+  for (auto& row : x.a)
+    for (auto& v : row) s = std::max(s, std::abs(v));
+  return s;
+}
+double herm_err3(const M3& x) {
+  double s = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s = std::max(s, std::abs(x.a[i][j] - std::conj(x.a[j][i])));
+  return s;
+}
+// Inverse of a Hermitian positive definite 3 x 3 block by Cholesky; false if
+// the (Hermitian part of the) block is not positive definite.
+bool hpd_inverse3(const M3& x, M3& inv) {
+  cplx L[3][3] = {};
+  for (int j = 0; j < 3; ++j) {
+    double d = 0.5 * (x.a[j][j].real() + x.a[j][j].real());
+    for (int k = 0; k < j; ++k) d -= std::norm(L[j][k]);
+    if (!(d > 0.0)) return false;
+    L[j][j] = std::sqrt(d);
+    for (int i = j + 1; i < 3; ++i) {
+      cplx s = 0.5 * (x.a[i][j] + std::conj(x.a[j][i]));
+      for (int k = 0; k < j; ++k) s -= L[i][k] * std::conj(L[j][k]);
+      L[i][j] = s / L[j][j].real();
+    }
+  }
+  // inverse of L, then inv = L^-* L^-1
+  cplx Li[3][3] = {};
+  for (int i = 0; i < 3; ++i) {
+    Li[i][i] = 1.0 / L[i][i].real();
+    for (int j = 0; j < i; ++j) {
+      cplx s = 0;
+      for (int k = j; k < i; ++k) s -= L[i][k] * Li[k][j];
+      Li[i][j] = s / L[i][i].real();
+    }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cplx s = 0;
+      for (int k = std::max(i, j); k < 3; ++k) s += std::conj(Li[k][i]) * Li[k][j];
+      inv.a[i][j] = s;
+    }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
+
+int nsf_set_medium_tensor(nsf_plan p, const nsf_c128* eps, const nsf_c128* mu, const nsf_c128* xi,
+                          const nsf_c128* zeta, int on_device) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  if (!eps || !mu || !xi || !zeta) return set_error(p, NSF_E_ARG, "a tensor field is NULL");
+  const long long n = p->geom.n;
+  const size_t cnt = 9 * (size_t)n;
+  std::vector<double2> h[4];
+  const double2* src[4] = {reinterpret_cast<const double2*>(eps), reinterpret_cast<const double2*>(mu),
+                           reinterpret_cast<const double2*>(xi), reinterpret_cast<const double2*>(zeta)};
+  if (on_device) {
+    const int rc = ensure_device(p);
+    if (rc) return rc;
+    for (int f = 0; f < 4; ++f) {
+      h[f].resize(cnt);
+      NSF_HIP(p, hipMemcpyAsync(h[f].data(), src[f], sizeof(double2) * cnt, hipMemcpyDeviceToHost, p->stream));
+      src[f] = h[f].data();
+    }
+    NSF_HIP(p, hipStreamSynchronize(p->stream));
+  }
+  std::vector<double2> M((size_t)n * kGenEntries);
+  for (long long g = 0; g < n; ++g) {
+    const M3 E = load3(src[0] + 9 * g), U = load3(src[1] + 9 * g), X = load3(src[2] + 9 * g),
+             Z = load3(src[3] + 9 * g);
+    const double scale = std::max({absmax3(E), absmax3(U), absmax3(X), absmax3(Z), 1.0});
+    for (const M3* t : {&E, &U, &X, &Z})
+      for (auto& row : t->a)
+        for (auto& v : row)
+          if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+            return set_error(p, NSF_E_ARG, "medium has a non-finite value at voxel " + std::to_string(g));
+    const std::string at = " at voxel " + std::to_string(g);
+    if (herm_err3(U) > 1e-14 * scale) return set_error(p, NSF_E_NOT_HHPD, "mu is not Hermitian" + at);
+    if (herm_err3(E) > 1e-14 * scale) return set_error(p, NSF_E_NOT_HHPD, "eps is not Hermitian" + at);
+    const M3 Xa = adj3(X);
+    double dz = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) dz = std::max(dz, std::abs(Xa.a[i][j] - Z.a[i][j]));
+    if (dz > 1e-14 * scale) return set_error(p, NSF_E_NOT_HHPD, "zeta differs from xi^*" + at);
+    M3 Ui, Fi;
+    if (!hpd_inverse3(U, Ui)) return set_error(p, NSF_E_NOT_HHPD, "mu is not positive definite" + at);
+    const M3 XUi = mul3(X, Ui);                 // xi mu^-1
+    const M3 UiZ = adj3(XUi);                   // mu^-1 zeta (zeta = xi^*, mu Hermitian)
+    M3 Phi = mul3(XUi, Z);                      // xi mu^-1 zeta
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Phi.a[i][j] = E.a[i][j] - Phi.a[i][j];
+    if (!hpd_inverse3(Phi, Fi))
+      return set_error(p, NSF_E_NOT_HHPD, "Phi = eps - xi mu^-1 zeta is not positive definite" + at);
+    const M3 M12 = mul3(UiZ, Fi);               // mu^-1 zeta Phi^-1
+    M3 M11 = mul3(M12, XUi);                    // mu^-1 zeta Phi^-1 xi mu^-1
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M11.a[i][j] += Ui.a[i][j];
+    // upper triangle of [[M11, M12], [M12^*, Fi]], row by row
+    auto ent = [&](int i, int j) -> cplx {
+      if (i < 3 && j < 3) return M11.a[i][j];
+      if (i < 3) return M12.a[i][j - 3];
+      return Fi.a[i - 3][j - 3];
+    };
+    double2* out = M.data() + (size_t)g * kGenEntries;
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i; j < 6; ++j, ++k) {
+        const cplx v = ent(i, j);
+        out[k] = make_double2(v.real(), v.imag());
+      }
+  }
+  const int rc = ensure_device(p);
+  if (rc) return rc;
+  if (!p->d_mgen) NSF_HIP(p, hipMalloc(&p->d_mgen, sizeof(double2) * M.size()));
+  NSF_HIP(p, hipMemcpyAsync(p->d_mgen, M.data(), sizeof(double2) * M.size(), hipMemcpyHostToDevice, p->stream));
+  NSF_HIP(p, hipStreamSynchronize(p->stream));
+  p->medium_kind = kMedGeneral;
+  return NSF_OK;
+}
 
 int nsf_set_medium_chiral(nsf_plan p, const double* eps, const double* gamma, int on_device) {
   return set_medium(p, kMedChiral, 0, 1, eps, gamma, on_device);

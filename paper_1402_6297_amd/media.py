@@ -99,6 +99,40 @@ def noise_chiral(n1, n2=None, n3=None, sigma_vox=2.0, seed=0,
     return eps.astype(np.float64), gamma.astype(np.float64)
 
 
+def random_general(n1, n2=None, n3=None, seed=0, xi_norm=0.6):
+    """Random bianisotropic voxel tensors (eps, mu, xi, zeta), each (n, 3, 3) complex.
+
+    mu = Q diag(d) Q^* with d ~ U[0.6, 1.6], eps = R diag(e) R^* with e ~ U[1, 13]
+    (Q, R random unitary), xi a complex normal matrix scaled to spectral norm
+    xi_norm * U[0, 1), zeta = xi^*.  With xi_norm <= 0.6 the bounds give
+    eps - xi mu^-1 zeta >= (1 - 0.36 / 0.6) I > 0, so every voxel meets the
+    Hermitian positive definite assumption by construction.
+    """
+    n2 = n1 if n2 is None else n2
+    n3 = n1 if n3 is None else n3
+    n = n1 * n2 * n3
+    rng = np.random.default_rng(seed)
+
+    def unitary():
+        a = rng.standard_normal((n, 3, 3)) + 1j * rng.standard_normal((n, 3, 3))
+        q, _ = np.linalg.qr(a)
+        return q
+
+    def herm(vals, q):
+        return np.einsum("gij,gj,gkj->gik", q, vals, q.conj())
+
+    mu = herm(rng.uniform(0.6, 1.6, (n, 3)), unitary())
+    eps = herm(rng.uniform(1.0, 13.0, (n, 3)), unitary())
+    a = rng.standard_normal((n, 3, 3)) + 1j * rng.standard_normal((n, 3, 3))
+    a /= np.linalg.norm(a, ord=2, axis=(1, 2))[:, None, None]
+    xi = a * (xi_norm * rng.random(n))[:, None, None]
+    zeta = np.conj(np.transpose(xi, (0, 2, 1)))
+    # exact Hermitian symmetry of eps and mu
+    eps = 0.5 * (eps + np.conj(np.transpose(eps, (0, 2, 1))))
+    mu = 0.5 * (mu + np.conj(np.transpose(mu, (0, 2, 1))))
+    return eps, mu, xi, np.ascontiguousarray(zeta)
+
+
 def homogeneous(n1, n2=None, n3=None, *, eps=1.0, gamma=0.0):
     """Constant (eps, gamma) fields."""
     n2 = n1 if n2 is None else n2

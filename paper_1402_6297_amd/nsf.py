@@ -29,6 +29,8 @@ NSF_E_NOMEM = -6
 NSF_E_HIP = -7
 NSF_E_STATE = -8
 
+NSF_MEDIUM_NONE, NSF_MEDIUM_CHIRAL, NSF_MEDIUM_PSEUDOCHIRAL, NSF_MEDIUM_GENERAL = 0, 1, 2, 3
+
 NSF_OPT_FFT_PATH = 1
 NSF_OPT_MID_COLS = 2
 NSF_OPT_CG_GRAPH = 3
@@ -39,7 +41,7 @@ NSF_OPT_CG_START = 7
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",
-    "nsf_set_medium_chiral", "nsf_set_medium_pseudochiral",
+    "nsf_set_medium_chiral", "nsf_set_medium_pseudochiral", "nsf_set_medium_tensor",
     "nsf_apply_Pr", "nsf_apply_Qr", "nsf_apply_PrH", "nsf_apply_QrH",
     "nsf_apply_Ar", "nsf_apply_Br", "nsf_profile_Ar", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
     "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
@@ -105,6 +107,7 @@ def lib():
         "nsf_plan_query": (I, [P, C.POINTER(C.c_longlong), C.POINTER(I), DP, DP]),
         "nsf_set_medium_chiral": (I, [P, VP, VP, I]),
         "nsf_set_medium_pseudochiral": (I, [P, I, I, VP, VP, I]),
+        "nsf_set_medium_tensor": (I, [P, VP, VP, VP, VP, I]),
         "nsf_apply_Pr": (I, [P, VP, VP]),
         "nsf_apply_Qr": (I, [P, VP, VP]),
         "nsf_apply_PrH": (I, [P, VP, VP]),
@@ -212,6 +215,21 @@ def nsf_set_medium_chiral(plan, eps, gamma):
 def nsf_set_medium_pseudochiral(plan, axis_a, axis_b, eps, gamma):
     keep, pe, pg, on_dev = _medium_ptrs(eps, gamma)
     return _check(lib().nsf_set_medium_pseudochiral(plan, int(axis_a), int(axis_b), pe, pg, on_dev), plan)
+
+
+def nsf_set_medium_tensor(plan, eps, mu, xi, zeta):
+    """General medium: four (n, 3, 3) complex128 tensor fields (numpy on the host, or
+    contiguous torch tensors on the device), voxel order g = i1 + n1 i2 + n1 n2 i3."""
+    fields = [eps, mu, xi, zeta]
+    try:
+        import torch
+        if isinstance(eps, torch.Tensor):
+            ptrs = [_dptr(t, "c128") for t in fields]
+            return _check(lib().nsf_set_medium_tensor(plan, *ptrs, 1), plan)
+    except ImportError:  # pragma: no cover
+        pass
+    keep = [np.ascontiguousarray(np.reshape(f, (-1, 3, 3)), dtype=np.complex128) for f in fields]
+    return _check(lib().nsf_set_medium_tensor(plan, *[C.c_void_p(k.ctypes.data) for k in keep], 0), plan)
 
 
 def _apply(name, plan, src, dst):
@@ -371,6 +389,9 @@ class Batch:
     def set_pseudochiral(self, i, axis_a, axis_b, eps, gamma):
         return nsf_set_medium_pseudochiral(self.plan(i), axis_a, axis_b, eps, gamma)
 
+    def set_tensor(self, i, eps, mu, xi, zeta):
+        return nsf_set_medium_tensor(self.plan(i), eps, mu, xi, zeta)
+
     def eigs(self, nev, **kw):
         return nsf_batch_eigs(self.handle, self.count, nev, **kw)
 
@@ -433,6 +454,9 @@ class Plan:
 
     def set_pseudochiral(self, axis_a, axis_b, eps, gamma):
         return nsf_set_medium_pseudochiral(self.handle, axis_a, axis_b, eps, gamma)
+
+    def set_tensor(self, eps, mu, xi, zeta):
+        return nsf_set_medium_tensor(self.handle, eps, mu, xi, zeta)
 
     def Ar(self, u, out):
         return nsf_apply_Ar(self.handle, u, out)

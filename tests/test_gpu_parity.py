@@ -494,3 +494,58 @@ def test_projected_cg_start_same_eigenpairs(batched):
     assert r0.max() <= 1e-9 and r1.max() <= 1e-9
     assert np.abs(om1 - om0).max() <= 1e-10 * om0.max()
     assert it1 < it0
+
+
+# ------------------------------------------------------------ general media
+
+GENERAL_CASES = [((4, 4, 4), (0.1, 0.2, 0.3)), ((16, 12, 10), (0.3, 0.1, 0.2)),
+                 ((64, 16, 48), (0.3, 0.0, 0.2)), ((32, 96, 16), (0.2, 0.4, 0.1))]
+
+
+@pytest.mark.parametrize("path", [0, 1, 2], ids=["auto", "generic", "twolevel"])
+@pytest.mark.parametrize("grid,k", GENERAL_CASES)
+def test_general_medium_Ar_matches_oracle(grid, k, path):
+    n = grid[0] * grid[1] * grid[2]
+    eps, mu, xi, zeta = media.random_general(*grid, seed=4)
+    tens = dict(eps=eps, mu=mu, xi=xi, zeta=zeta)
+    u = media.random_vector(4 * n, 9)
+    with nsf.Plan(grid, k) as P:
+        P.set_option(nsf.NSF_OPT_FFT_PATH, path)
+        P.set_tensor(eps, mu, xi, zeta)
+        assert P.query()["medium_kind"] == nsf.NSF_MEDIUM_GENERAL
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        assert rel(host(out), nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+
+
+def test_general_medium_reproduces_chiral_path():
+    """The chiral sphere given as general tensors (device pointers) gives the chiral A_r."""
+    grid, k = (32, 32, 32), (0.1, 0.2, 0.3)
+    n = 32 ** 3
+    eps, gam = media.sphere_chiral(32)
+    t = medium.tensors_chiral(eps, gam)
+    u = dev(media.random_vector(4 * n, 10))
+    outs = []
+    for general in (False, True):
+        with nsf.Plan(grid, k) as P:
+            if general:
+                P.set_tensor(*[dev(np.ascontiguousarray(t[key])) for key in ("eps", "mu", "xi", "zeta")])
+            else:
+                P.set_chiral(eps, gam)
+            out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+            P.Ar(u, out)
+            outs.append(host(out))
+    assert rel(outs[1], outs[0]) < 1e-12
+
+
+def test_general_medium_eigs_match_dense_4():
+    grid, k = (4, 4, 4), (0.1, 0.2, 0.3)
+    eps, mu, xi, zeta = media.random_general(4, seed=6)
+    tens = dict(eps=eps, mu=mu, xi=xi, zeta=zeta)
+    om_all = nfgep.nfgep_dense(grid, k, tens)
+    ref = np.sort(om_all[om_all > 0])[:6]
+    with nsf.Plan(grid, k) as P:
+        P.set_tensor(eps, mu, xi, zeta)
+        st, om, res, _ = P.eigs(6, res_tol=1e-10, cg_rtol=1e-12)
+    assert st == nsf.NSF_OK
+    assert np.abs(om - ref).max() < 1e-10 * ref.max()
