@@ -141,6 +141,25 @@ typedef struct {
 } nsf_tune;
 int nsf_plan_autotune(nsf_plan plan, int reps, nsf_tune* result);
 
+/*
+ * Caller-provided workspace (for example from PyTorch's caching allocator).
+ * nsf_plan_workspace_size: the device bytes an nsf_eigs call with this nev and
+ *   max_basis (as nsf_eigs; 0 for the default) needs for the six field arrays
+ *   (96 n B), the CG and Lanczos-step vectors (384 n B), the basis V and A_r V
+ *   (2 (m+1) 64 n B) and the projected-matrix scratch, alignment included.
+ * nsf_plan_set_workspace: the plan carves those buffers from dev_ptr (any
+ *   alignment; the caller keeps ownership and must keep it alive and unused
+ *   elsewhere until the plan is destroyed or given another workspace), frees
+ *   its own copies of them, and never allocates them again.  An eigensolve that
+ *   needs a larger basis than fits returns NSF_E_NOMEM.  dev_ptr = NULL returns
+ *   to library-allocated buffers.  NSF_E_ARG if bytes cannot hold the fields,
+ *   the CG vectors and a 2-vector basis.  Synchronises the plan's stream; the
+ *   contents of the old buffers are not carried over.  Tables, reduction
+ *   scratch and the medium stay library-allocated (small, or set once).
+ */
+int nsf_plan_workspace_size(nsf_plan plan, int nev, int max_basis, size_t* bytes);
+int nsf_plan_set_workspace(nsf_plan plan, void* dev_ptr, size_t bytes);
+
 /* Free the plan and all device memory it owns.  NULL is accepted. */
 void nsf_plan_destroy(nsf_plan plan);
 

@@ -793,6 +793,7 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
     if (w1 < B)
       for (int i = w0; i < w1; ++i) {
         nsf_plan p = b->plans[i];
+        if (p->ws) continue;  // caller-provided storage stays
         NSF_HIP(p, hipStreamSynchronize(b->stream));
         if (p->d_basis) NSF_HIP(p, hipFree(p->d_basis));
         p->d_basis = nullptr;

@@ -307,6 +307,11 @@ struct nsf_plan_s {
   double2* d_basis = nullptr;  // V and AV
   size_t basis_vectors = 0;    // capacity of V (and of AV)
 
+  // caller-provided workspace (nsf_plan_set_workspace): fields, CG vectors,
+  // basis and small matrices are carved from it and never freed by the plan
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+
   // options (nsf_plan_set_option)
   int opt_fft_path = 0;     // 0 auto, 1 generic LDS-staged, 2 two-level without single-wave
   int opt_mid_cols = 16;    // pencils per workgroup of the fused z pass
@@ -339,6 +344,11 @@ hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mi
 hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip);
 int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
                  double* relres, long long* matvecs);
+// Bytes of the caller workspace for a basis of m + 1 vectors (fields, CG, V, A_r V, m x m).
+size_t workspace_bytes(long long n, int m);
+// Part of the caller workspace: 0 fields, 1 CG vectors, 2 basis (capacity in
+// vectors to *basis_cap), 3 small matrices; nullptr when the plan has none.
+double2* ws_part(nsf_plan p, int which, size_t* basis_cap = nullptr);
 int ensure_cg(nsf_plan p);
 bool cg_fusable(nsf_plan p);
 CgFuse cg_fuse_of(nsf_plan p, double2* x);

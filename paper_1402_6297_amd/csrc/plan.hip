@@ -67,7 +67,10 @@ int ensure_device(nsf_plan p) {
   p->tabs.lam = p->d_tables;
   p->tabs.twist = p->d_tables + ntab;
   p->tabs.tw = p->d_tables + 2 * ntab;
-  NSF_HIP(p, hipMalloc(&p->d_fields, sizeof(double2) * 6 * (size_t)g.n));
+  if (p->ws)
+    p->d_fields = ws_part(p, 0);
+  else
+    NSF_HIP(p, hipMalloc(&p->d_fields, sizeof(double2) * 6 * (size_t)g.n));
   NSF_HIP(p, hipMalloc(&p->d_partial,
                        sizeof(double2) * (size_t)(kPartialSlots + kCoefSlots + kResSlots + kMidSlots)));
   p->d_coef = p->d_partial + kPartialSlots;
@@ -289,7 +292,7 @@ void nsf_plan_destroy(nsf_plan p) {
   if (p->dev_ready) {
     hipStreamSynchronize(p->stream);
     hipFree(p->d_tables);
-    hipFree(p->d_fields);
+    if (!p->ws) hipFree(p->d_fields);
     hipFree(p->d_partial);
     hipFree(p->d_state);
     hipHostFree(p->h_state);
@@ -298,11 +301,50 @@ void nsf_plan_destroy(nsf_plan p) {
     hipHostFree(p->h_res);
     if (p->d_medium) hipFree(p->d_medium);
     if (p->d_mgen) hipFree(p->d_mgen);
-    if (p->d_cg) hipFree(p->d_cg);
-    if (p->d_basis) hipFree(p->d_basis);
-    if (p->d_small) hipFree(p->d_small);
+    if (p->d_cg && !p->ws) hipFree(p->d_cg);
+    if (p->d_basis && !p->ws) hipFree(p->d_basis);
+    if (p->d_small && !p->ws) hipFree(p->d_small);
   }
   delete p;
+}
+
+int nsf_plan_workspace_size(nsf_plan p, int nev, int max_basis, size_t* bytes) {
+  if (!p || !bytes) return set_error(p, NSF_E_ARG, "NULL argument");
+  const long long len = 4 * p->geom.n;
+  if (nev < 1 || nev > 256 || 2LL * nev >= len) return set_error(p, NSF_E_ARG, "nev out of range");
+  int m = max_basis > 0 ? max_basis : std::max(3 * nev, nev + 8);
+  if (m < nev + 2) m = nev + 2;
+  if (m > 510) m = 510;
+  if (m >= len) m = (int)len - 1;
+  *bytes = workspace_bytes(p->geom.n, m);
+  return NSF_OK;
+}
+
+int nsf_plan_set_workspace(nsf_plan p, void* dev_ptr, size_t bytes) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  const long long n = p->geom.n;
+  if (dev_ptr && bytes < workspace_bytes(n, 1))
+    return set_error(p, NSF_E_ARG, "workspace smaller than the fields, CG vectors and a 2-vector basis");
+  if (p->dev_ready) NSF_HIP(p, hipStreamSynchronize(p->stream));
+  // release what the plan allocated itself (or drop the old workspace's parts)
+  if (!p->ws) {
+    if (p->d_fields) NSF_HIP(p, hipFree(p->d_fields));
+    if (p->d_cg) NSF_HIP(p, hipFree(p->d_cg));
+    if (p->d_basis) NSF_HIP(p, hipFree(p->d_basis));
+    if (p->d_small) NSF_HIP(p, hipFree(p->d_small));
+  }
+  p->d_fields = p->d_cg = p->d_basis = p->d_small = nullptr;
+  p->basis_vectors = 0;
+  p->small_cap = 0;
+  p->ws = static_cast<char*>(dev_ptr);
+  p->ws_bytes = dev_ptr ? bytes : 0;
+  if (p->dev_ready) {
+    if (p->ws)
+      p->d_fields = ws_part(p, 0);
+    else
+      NSF_HIP(p, hipMalloc(&p->d_fields, sizeof(double2) * 6 * (size_t)n));
+  }
+  return NSF_OK;
 }
 
 int nsf_plan_set_option(nsf_plan p, int option, int value) {

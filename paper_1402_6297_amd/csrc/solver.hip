@@ -22,15 +22,60 @@
 
 namespace nsf {
 
+// Caller workspace layout, each part aligned to 256 bytes:
+// [fields 6n][CG 24n][V, A_r V: 2 (m+1) 4n][small m x m] (double2 units).
+namespace {
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t workspace_bytes(long long n, int m) {
+  const size_t d2 = sizeof(double2);
+  return al256(d2 * 6 * (size_t)n) + al256(d2 * 24 * (size_t)n) + al256(d2 * 2 * (size_t)(m + 1) * 4 * n) +
+         al256(d2 * (size_t)m * m) + 256;
+}
+
+// Part `which` (0 fields, 1 CG, 2 basis, 3 small) of the caller workspace, or
+// nullptr when there is none; *cap receives the basis capacity in vectors.
+double2* ws_part(nsf_plan p, int which, size_t* basis_cap) {
+  if (!p->ws) return nullptr;
+  const size_t d2 = sizeof(double2);
+  const long long n = p->geom.n;
+  char* base = reinterpret_cast<char*>(al256(reinterpret_cast<size_t>(p->ws)));
+  const size_t used0 = (size_t)(base - p->ws);
+  const size_t f = al256(d2 * 6 * (size_t)n), c = al256(d2 * 24 * (size_t)n);
+  if (which == 0) return reinterpret_cast<double2*>(base);
+  if (which == 1) return reinterpret_cast<double2*>(base + f);
+  // the rest holds V, A_r V for v vectors and a (v-1) x (v-1) matrix
+  const size_t rest = p->ws_bytes > used0 + f + c ? p->ws_bytes - used0 - f - c : 0;
+  size_t v = 0;
+  while (al256(d2 * 2 * (v + 1) * 4 * (size_t)n) + al256(d2 * v * v) <= rest) ++v;
+  if (basis_cap) *basis_cap = v;
+  if (which == 2) return reinterpret_cast<double2*>(base + f + c);
+  return reinterpret_cast<double2*>(base + f + c + al256(d2 * 2 * (v ? v : 1) * 4 * (size_t)n));
+}
+
 // workspace for CG and the Lanczos step: r, p, q, w, z, b (six 4n vectors)
 int ensure_cg(nsf_plan p) {
   int rc = ensure_device(p);
   if (rc) return rc;
+  if (p->ws) {
+    p->d_cg = ws_part(p, 1);
+    return NSF_OK;
+  }
   if (!p->d_cg) NSF_HIP(p, hipMalloc(&p->d_cg, sizeof(double2) * 6 * 4 * (size_t)p->geom.n));
   return NSF_OK;
 }
 
 int ensure_basis(nsf_plan p, size_t vectors) {
+  if (p->ws) {
+    size_t cap = 0;
+    p->d_basis = ws_part(p, 2, &cap);
+    p->basis_vectors = cap;
+    if (cap < vectors)
+      return set_error(p, NSF_E_NOMEM, "the caller workspace holds a basis of " + std::to_string(cap) +
+                                           " vectors, " + std::to_string(vectors) + " needed");
+    return NSF_OK;
+  }
   if (p->basis_vectors >= vectors) return NSF_OK;
   if (p->d_basis) {
     NSF_HIP(p, hipStreamSynchronize(p->stream));
@@ -44,6 +89,13 @@ int ensure_basis(nsf_plan p, size_t vectors) {
 }
 
 int ensure_small(nsf_plan p, size_t count) {
+  if (p->ws) {
+    size_t cap = 0;
+    p->d_small = ws_part(p, 3, &cap);
+    p->small_cap = cap ? (cap - 1) * (cap - 1) : 0;
+    if (p->small_cap < count) return set_error(p, NSF_E_NOMEM, "the caller workspace is too small");
+    return NSF_OK;
+  }
   if (p->small_cap >= count) return NSF_OK;
   if (p->d_small) {
     NSF_HIP(p, hipStreamSynchronize(p->stream));

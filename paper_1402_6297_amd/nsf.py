@@ -46,7 +46,7 @@ EXPORTED = [
     "nsf_apply_Ar", "nsf_apply_Br", "nsf_profile_Ar", "nsf_cg_solve", "nsf_eigs", "nsf_eig_grad",
     "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
     "nsf_batch_create", "nsf_batch_plan", "nsf_batch_eigs", "nsf_batch_destroy",
-    "nsf_plan_autotune", "nsf_batch_autotune",
+    "nsf_plan_autotune", "nsf_batch_autotune", "nsf_plan_workspace_size", "nsf_plan_set_workspace",
 ]
 
 
@@ -126,6 +126,8 @@ def lib():
                                C.POINTER(I)]),
         "nsf_batch_destroy": (None, [P]),
         "nsf_plan_autotune": (I, [P, I, C.POINTER(nsf_tune)]),
+        "nsf_plan_workspace_size": (I, [P, I, I, C.POINTER(C.c_size_t)]),
+        "nsf_plan_set_workspace": (I, [P, VP, C.c_size_t]),
         "nsf_batch_autotune": (I, [P, I, C.POINTER(I)]),
         "nsf_status_string": (C.c_char_p, [I]),
         "nsf_last_error": (C.c_char_p, [P]),
@@ -352,6 +354,20 @@ def nsf_plan_autotune(plan, reps=10):
     return t.as_dict()
 
 
+def nsf_plan_workspace_size(plan, nev, max_basis=0):
+    b = C.c_size_t()
+    _check(lib().nsf_plan_workspace_size(plan, int(nev), int(max_basis), C.byref(b)), plan)
+    return b.value
+
+
+def nsf_plan_set_workspace(plan, buf):
+    """buf: a contiguous torch tensor on the device (kept alive by the caller), or None."""
+    if buf is None:
+        return _check(lib().nsf_plan_set_workspace(plan, None, 0), plan)
+    nbytes = buf.numel() * buf.element_size()
+    return _check(lib().nsf_plan_set_workspace(plan, C.c_void_p(buf.data_ptr()), nbytes), plan)
+
+
 def nsf_batch_autotune(batch, reps=10):
     shapes = C.c_int()
     _check(lib().nsf_batch_autotune(batch, int(reps), C.byref(shapes)))
@@ -490,3 +506,10 @@ class Plan:
 
     def autotune(self, reps=10):
         return nsf_plan_autotune(self.handle, reps)
+
+    def workspace_size(self, nev, max_basis=0):
+        return nsf_plan_workspace_size(self.handle, nev, max_basis)
+
+    def set_workspace(self, buf):
+        self._workspace = buf  # keep the caller's tensor alive with the plan
+        return nsf_plan_set_workspace(self.handle, buf)

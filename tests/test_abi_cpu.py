@@ -163,3 +163,22 @@ def test_general_medium_validation(breaker, msg):
         assert msg in str(e.value) and f"voxel {g}" in str(e.value)
     finally:
         nsf.nsf_plan_destroy(p)
+
+
+def test_workspace_size_and_validation():
+    import ctypes
+
+    p = nsf.nsf_plan_create(8, 8, 8, 1.0, (0.1, 0.2, 0.3), stream=0)
+    try:
+        n = 512
+        b4 = nsf.nsf_plan_workspace_size(p, 4)
+        b10 = nsf.nsf_plan_workspace_size(p, 10)
+        b10m = nsf.nsf_plan_workspace_size(p, 10, max_basis=60)
+        # fields 6n + CG 24n + basis 2 (m+1) 4n complex values, m = max(3 nev, nev + 8)
+        assert b4 >= 16 * n * (6 + 24 + 2 * 13 * 4) and b10 > b4 and b10m > b10
+        # too small for fields + CG + a 2-vector basis: refused before any device use
+        assert nsf.lib().nsf_plan_set_workspace(p, ctypes.c_void_p(0x100000), 1024) == nsf.NSF_E_ARG
+        with pytest.raises(nsf.NsfError):
+            nsf.nsf_plan_workspace_size(p, 0)
+    finally:
+        nsf.nsf_plan_destroy(p)

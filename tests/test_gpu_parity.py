@@ -549,3 +549,27 @@ def test_general_medium_eigs_match_dense_4():
         st, om, res, _ = P.eigs(6, res_tol=1e-10, cg_rtol=1e-12)
     assert st == nsf.NSF_OK
     assert np.abs(om - ref).max() < 1e-10 * ref.max()
+
+
+def test_caller_workspace_gives_identical_results():
+    """Buffers carved from a caller tensor: the same eigenpairs bit for bit; a basis
+    larger than the workspace holds is refused with NSF_E_NOMEM; None returns to
+    library allocation."""
+    grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
+    eps, gam = media.sphere_chiral(16)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st0, om0, r0, _ = P.eigs(6, res_tol=1e-9, cg_rtol=1e-11, seed=3)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        nbytes = P.workspace_size(6)
+        buf = torch.empty(nbytes + 8, dtype=torch.uint8, device="cuda")[8:]  # unaligned on purpose
+        P.set_workspace(buf)
+        st1, om1, r1, _ = P.eigs(6, res_tol=1e-9, cg_rtol=1e-11, seed=3)
+        with pytest.raises(nsf.NsfError) as e:
+            P.eigs(12, res_tol=1e-9, cg_rtol=1e-11)
+        assert e.value.status == nsf.NSF_E_NOMEM
+        P.set_workspace(None)
+        st2, om2, r2, _ = P.eigs(6, res_tol=1e-9, cg_rtol=1e-11, seed=3)
+    assert st0 == st1 == st2 == nsf.NSF_OK
+    assert np.array_equal(om0, om1) and np.array_equal(om0, om2)
