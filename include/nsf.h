@@ -281,6 +281,17 @@ int nsf_eigs(nsf_plan plan, int nev, double res_tol, double cg_rtol,
              nsf_stats* stats);
 
 /*
+ * Electric and magnetic fields of a pencil eigenvector (Algorithm 1, last
+ * step): [E; H] = B^{-1} diag(P_r, Q_r) y, B the medium matrix of the GEP
+ * (Sec. 3).  y: device 4n vector (as returned by nsf_eigs); eh: device 6n,
+ * [E_x; E_y; E_z; H_x; H_y; H_z], n each, voxel order g, carrying the Bloch
+ * phase of k.  The pair (omega, [E; H]) then solves
+ * diag(C, C^*) [E; H] = omega B [E; H].  Needs a medium (NSF_E_STATE).
+ * Asynchronous.
+ */
+int nsf_fields(nsf_plan plan, const nsf_c128* y4n, nsf_c128* eh6n);
+
+/*
  * Gradient of S = sum_j w_j omega_j with respect to the per-voxel eps and
  * gamma of a chiral medium, by the Hellmann-Feynman rule for the HHPD pencil
  * (Thm 4.2): d omega = omega y^* dA_r y for A_r-normalised y.  With

@@ -47,6 +47,7 @@ EXPORTED = [
     "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
     "nsf_batch_create", "nsf_batch_plan", "nsf_batch_eigs", "nsf_batch_destroy",
     "nsf_plan_autotune", "nsf_batch_autotune", "nsf_plan_workspace_size", "nsf_plan_set_workspace",
+    "nsf_fields",
 ]
 
 
@@ -127,6 +128,7 @@ def lib():
         "nsf_batch_destroy": (None, [P]),
         "nsf_plan_autotune": (I, [P, I, C.POINTER(nsf_tune)]),
         "nsf_plan_workspace_size": (I, [P, I, I, C.POINTER(C.c_size_t)]),
+        "nsf_fields": (I, [P, VP, VP]),
         "nsf_plan_set_workspace": (I, [P, VP, C.c_size_t]),
         "nsf_batch_autotune": (I, [P, I, C.POINTER(I)]),
         "nsf_status_string": (C.c_char_p, [I]),
@@ -236,6 +238,10 @@ def nsf_set_medium_tensor(plan, eps, mu, xi, zeta):
 
 def _apply(name, plan, src, dst):
     return _check(getattr(lib(), name)(plan, _dptr(src, "c128"), _dptr(dst, "c128")), plan)
+
+
+def nsf_fields(plan, y4n, eh6n):
+    return _apply("nsf_fields", plan, y4n, eh6n)
 
 
 def nsf_apply_Pr(plan, y2n, x3n):
@@ -479,6 +485,9 @@ class Plan:
 
     def profile_Ar(self, u, out, reps=20):
         return nsf_profile_Ar(self.handle, u, out, reps)
+
+    def fields(self, y, eh):
+        return nsf_fields(self.handle, y, eh)
 
     def Br(self, u, out):
         return nsf_apply_Br(self.handle, u, out)

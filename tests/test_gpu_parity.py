@@ -573,3 +573,58 @@ def test_caller_workspace_gives_identical_results():
         st2, om2, r2, _ = P.eigs(6, res_tol=1e-9, cg_rtol=1e-11, seed=3)
     assert st0 == st1 == st2 == nsf.NSF_OK
     assert np.array_equal(om0, om1) and np.array_equal(om0, om2)
+
+
+# ------------------------------------------------------- field recovery
+
+@pytest.mark.parametrize("grid,k,kind", [((4, 4, 4), (0.1, 0.2, 0.3), "noise"),
+                                         ((16, 12, 10), (0.3, 0.1, 0.2), "general"),
+                                         ((8, 8, 8), (0.2, 0.3, 0.1), "pseudo_xz"),
+                                         ((32, 16, 48), (0.1, 0.4, 0.2), "chiral")])
+def test_fields_match_oracle(grid, k, kind):
+    """[E; H] = B^{-1} diag(P_r, Q_r) y against the oracle's twisted basis applies and
+    a sparse solve with the GEP's medium matrix B."""
+    import scipy.sparse.linalg as spla
+
+    n = grid[0] * grid[1] * grid[2]
+    if kind == "general":
+        eps, mu, xi, zeta = media.random_general(*grid, seed=2)
+        tens = dict(eps=eps, mu=mu, xi=xi, zeta=zeta)
+    else:
+        eps, gam, tens, pair = _medium(kind, grid)
+    y = media.random_vector(4 * n, 12)
+    with nsf.Plan(grid, k) as P:
+        if kind == "general":
+            P.set_tensor(eps, mu, xi, zeta)
+        else:
+            _set(P, eps, gam, pair)
+        eh = torch.empty(6 * n, dtype=torch.complex128, device="cuda")
+        P.fields(dev(y), eh)
+        got = host(eh)
+    rhs = np.concatenate([basis.apply_Pr(y[:2 * n], grid, k), basis.apply_Qr(y[2 * n:], grid, k)])
+    ref = spla.spsolve(medium.B_matrix(tens).tocsc(), rhs)
+    assert rel(got, ref) < 1e-12
+
+
+def test_fields_of_eigenpairs_solve_the_gep_8():
+    """The recovered fields of converged pencil eigenvectors solve the original GEP
+    diag(C, C^*) x = omega B x (Sec. 3) to the pencil residual."""
+    grid, k = (8, 8, 8), (0.1, 0.2, 0.3)
+    n = 512
+    eps, gam = media.sphere_chiral(8)
+    tens = medium.tensors_chiral(eps, gam)
+    nev = 4
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        Y = torch.empty(nev * 4 * n, dtype=torch.complex128, device="cuda")
+        st, om, res, _ = P.eigs(nev, res_tol=1e-11, cg_rtol=1e-13, Y=Y)
+        assert st == nsf.NSF_OK
+        eh = torch.empty(6 * n, dtype=torch.complex128, device="cuda")
+        C = yee.C_matrix(grid, k)
+        Bm = medium.B_matrix(tens)
+        for j in range(nev):
+            P.fields(Y[j * 4 * n:(j + 1) * 4 * n], eh)
+            x = host(eh)
+            lhs = np.concatenate([C @ x[:3 * n], C.conj().T @ x[3 * n:]])
+            rhsv = om[j] * (Bm @ x)
+            assert np.linalg.norm(lhs - rhsv) <= 1e-9 * np.linalg.norm(rhsv)
