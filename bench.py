@@ -75,8 +75,9 @@ def batch_leg(name, log=sys.stderr):
 
     grids, ks, med, nev = batch_instances(name)
     kw = dict(res_tol=1e-8, cg_rtol=1e-10, seed=0)
-    # plain: one plan at a time
-    t0 = time.perf_counter()
+    # plain: one plan at a time; plan set-up (tables, medium upload) is outside
+    # the timed region in both schedules, only the eigensolves are timed
+    t_plain = 0.0
     plain_pairs, plain_mv = 0, 0
     for i, (g, k, m) in enumerate(zip(grids, ks, med)):
         with nsf.Plan(g, k) as P:
@@ -84,12 +85,14 @@ def batch_leg(name, log=sys.stderr):
                 P.set_chiral(m[1], m[2])
             else:
                 P.set_pseudochiral(0, 1, m[1], m[2])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             st, om, res, stats = P.eigs(nev, seed=kw["seed"] + 1000003 * i, res_tol=kw["res_tol"],
                                         cg_rtol=kw["cg_rtol"])
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
             plain_pairs += stats["converged"]
             plain_mv += stats["matvecs"]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
     print(f"[bench] {name} plain: {len(grids)} instances, {t_plain:.1f} s", file=log, flush=True)
     with nsf.Batch(grids, ks) as B:
         for i, m in enumerate(med):
@@ -99,7 +102,10 @@ def batch_leg(name, log=sys.stderr):
                 B.set_pseudochiral(i, 0, 1, m[1], m[2])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        shapes = B.autotune(reps=5)  # tiling per grid shape, inside the timed region
+        shapes = B.autotune(reps=5)  # tiling per grid shape (set-up, reported apart)
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t0
+        t0 = time.perf_counter()
         st, om, res, stats, wave = B.eigs(nev, **kw)
         torch.cuda.synchronize()
         t_batch = time.perf_counter() - t0
@@ -108,9 +114,69 @@ def batch_leg(name, log=sys.stderr):
     return {"workload": name, "instances": len(grids), "nev": nev, "wave": wave,
             "eigenpairs_per_s_batched": round(pairs / t_batch, 4),
             "eigenpairs_per_s_plain": round(plain_pairs / t_plain, 4),
-            "s_batched": round(t_batch, 3), "s_plain": round(t_plain, 3),
+            "s_batched": round(t_batch, 3), "s_plain": round(t_plain, 3), "s_autotune": round(t_tune, 3),
             "max_residual": float(res.max()), "status": st,
             "grids": sorted(set(f"{g[0]}^3" for g in grids))}
+
+
+def median_apply_us(P, u, out, reps=100, warm=10):
+    """Median of `reps` individually timed A_r applies (HIP events on the plan's
+    stream, which is torch's current stream), after `warm` untimed ones."""
+    import torch
+
+    for _ in range(warm):
+        P.Ar(u, out)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        P.Ar(u, out)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) * 1e3 for a, b in ev]))
+
+
+def extra_workloads(log=sys.stderr):
+    """The other configurations, one small measurement each: the 128^3 rods apply
+    (second headline medium), the 64^3 sphere eigensolve and the 16^3 one."""
+    import torch
+
+    from paper_1402_6297_amd import media, nsf
+
+    out = {}
+    n = 128 ** 3
+    with nsf.Plan((128, 128, 128), (0.1, 0.2, 0.3)) as P:
+        P.set_pseudochiral(0, 1, *media.rods_pseudochiral(128))
+        u = torch.from_numpy(media.random_vector(4 * n, 0)).to("cuda")
+        o = torch.empty_like(u)
+        us = median_apply_us(P, u, o)
+        out["rods128_apply"] = {"us_median": round(us, 2),
+                                "GBps_alg": round(BYTES_PER_APPLY_PER_N * n / (us * 1e-6) / 1e9, 2),
+                                "frac": round(BYTES_PER_APPLY_PER_N * n / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del u, o
+    for name, grid, k in (("sphere64_eigs", (64, 64, 64), (0.25, 0.0, 0.0)),
+                          ("sphere16_eigs", (16, 16, 16), (0.1, 0.2, 0.3))):
+        with nsf.Plan(grid, k) as P:
+            P.set_chiral(*media.sphere_chiral(grid[0]))
+            P.eigs(10, res_tol=1e-8, cg_rtol=1e-10)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, om, res, stats = P.eigs(10, res_tol=1e-8, cg_rtol=1e-10)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            nn = grid[0] * grid[1] * grid[2]
+            nn_apply = None
+            if grid[0] >= 64:
+                u = torch.from_numpy(media.random_vector(4 * nn, 0)).to("cuda")
+                nn_apply = median_apply_us(P, u, torch.empty_like(u))
+            out[name] = {"status": st, "s_per_solve": round(dt, 4), "omega": [round(x, 10) for x in om.tolist()],
+                         "max_residual": float(res.max()), "matvecs": stats["matvecs"],
+                         "cg_iters_avg": round(stats["cg_iters_avg"], 2), "lanczos_steps": stats["lanczos_steps"],
+                         "restarts": stats["restarts"],
+                         "value_GBps": round(BYTES_PER_APPLY_PER_N * nn * stats["matvecs"] / dt / 1e9, 2)}
+            if nn_apply:
+                out[name]["apply_us_median"] = round(nn_apply, 2)
+        print(f"[bench] {name}: {out[name]['s_per_solve']} s", file=log, flush=True)
+    return out
 
 
 def grad_leg(nvox, log=sys.stderr, h=1e-6, nev=4):
@@ -277,6 +343,7 @@ def main():
     ap.add_argument("--workload", default="sphere128", choices=sorted(WORKLOADS))
     ap.add_argument("--nev", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the rods / 64^3 / 16^3 measurements")
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--fft-path", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_FFT_PATH)")
     ap.add_argument("--mid-cols", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_MID_COLS)")
@@ -356,6 +423,7 @@ def main():
     torch.cuda.synchronize()
     pass_ms, apply_ms = P.profile_Ar(u, out, reps=args.matvec_reps)
     b_alg = BYTES_PER_APPLY_PER_N * n
+    apply_ms = median_apply_us(P, u, out) * 1e-3  # headline: median of 100 timed applies
     apply_gbps = b_alg / (apply_ms * 1e-3) / 1e9
     traffic = None
     tpath = os.path.join(ROOT, "profiles", f"ar_apply_traffic_{args.workload}.json")
@@ -406,18 +474,23 @@ def main():
                    "grid": list(grid), "k": list(k), "nev": nev, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": round(apply_gbps, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(apply_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     "kernel": "A_r apply (all kernels of one apply, 336 n B algorithmic)",
+                     "kernel": "A_r apply (all five kernels of one apply, 336 n B algorithmic; median of 100 applies timed with HIP events)",
                      "kernel_us": [round(x * 1e3, 2) for x in pass_ms]},
         "device": dev_info,
         "autotune": tuned,
-        "matvec": {"us_per_apply": round(apply_ms * 1e3, 2), "GBps_alg": round(apply_gbps, 2),
-                   "bytes_alg": b_alg},
+        "matvec": {"us_per_apply_median": round(apply_ms * 1e3, 2), "GBps_alg": round(apply_gbps, 2),
+                   "bytes_alg": b_alg, "traffic_bytes": traffic,
+                   "traffic_GBps": round(traffic / (apply_ms * 1e-3) / 1e9, 2) if traffic else None},
         "eigs": {"status": st, "omega": [round(x, 12) for x in om.tolist()],
                  "max_residual": float(res.max()), "eigenpairs_per_s": round(tot_pairs / elapsed, 4),
                  "matvecs_per_solve": stats["matvecs"], "cg_iters_avg": round(stats["cg_iters_avg"], 2),
                  "lanczos_steps": stats["lanczos_steps"], "restarts": stats["restarts"],
-                 "s_per_solve": round(elapsed / args.steps, 3)},
+                 "s_per_solve": round(elapsed / args.steps, 3),
+                 "ms_phases": {"cg": round(stats["ms_cg"], 1), "gram_schmidt": round(stats["ms_orth"], 1),
+                               "restart_refine": round(stats["ms_restart"], 1)}},
     }
+    if not args.no_extra:
+        line["other_configs"] = extra_workloads()
     if args.batch != "none":
         line["batch"] = batch_leg(args.batch)
     if args.grad:

@@ -54,6 +54,10 @@ typedef struct {
   double cg_iters_avg;       /* cg_iters_total / cg_solves                      */
   double ms_total;           /* wall time of the call (host clock)              */
   double bytes_alg;          /* algorithmic HBM bytes of the A_r applies        */
+  double ms_cg;              /* eigensolver phases (host clock, for a batch the */
+  double ms_orth;            /*   whole batch's time in each phase): CG solves   */
+  double ms_restart;         /*   and exact applies; Gram-Schmidt and basis      */
+                             /*   admission; restarts and the final refinement   */
 } nsf_stats;
 
 enum {
@@ -292,6 +296,17 @@ int nsf_eigs(nsf_plan plan, int nev, double res_tol, double cg_rtol,
 int nsf_fields(nsf_plan plan, const nsf_c128* y4n, nsf_c128* eh6n);
 
 /*
+ * Start block for the plan's next eigensolve (nsf_eigs, or its instance in
+ * nsf_batch_eigs): count device 4n vectors at Y0_dev (column j at Y0_dev + j*4n,
+ * for example the Ritz vectors of a neighbouring Bloch vector).  The Lanczos
+ * start vector becomes sum_j c_j Y0_j with seeded complex normal c_j, plus the
+ * seeded normal vector at 1e-3 of its size.  The block is read at the start of
+ * that solve (the caller keeps it alive until the call returns) and is then
+ * forgotten.  count = 0 clears it.  0 <= count <= 512, else NSF_E_ARG.
+ */
+int nsf_eigs_set_start(nsf_plan plan, const nsf_c128* Y0_dev, int count);
+
+/*
  * Gradient of S = sum_j w_j omega_j with respect to the per-voxel eps and
  * gamma of a chiral medium, by the Hellmann-Feynman rule for the HHPD pencil
  * (Thm 4.2): d omega = omega y^* dA_r y for A_r-normalised y.  With
@@ -325,7 +340,9 @@ int nsf_eig_grad(nsf_plan plan, int nev, const double* omega_host,
  * nsf_batch_plan: borrow instance i's plan (owned by the batch) to set its
  *   medium or options, or to call single-instance functions on it.
  * nsf_batch_eigs: as nsf_eigs for every instance; omega_host and resid_host
- *   are count x nev (row i for instance i), stats count entries (nullable).
+ *   are count x nev (row i for instance i), stats count entries (nullable),
+ *   Y_dev (nullable) count device pointers (each nullable) that receive the
+ *   instance's 4n x nev Ritz vectors as nsf_eigs's Y_dev.
  *   Instances run in waves sized to free device memory; *wave_size (nullable)
  *   receives the wave length.  Returns NSF_OK when every instance converged,
  *   NSF_NOT_CONVERGED otherwise, or an error.  Synchronises.
@@ -336,7 +353,8 @@ int nsf_batch_create(nsf_batch* out, int count, const int* grids, const double* 
 int nsf_batch_plan(nsf_batch batch, int i, nsf_plan* plan);
 int nsf_batch_eigs(nsf_batch batch, int nev, double res_tol, double cg_rtol, int max_basis,
                    int max_restarts, unsigned long long seed, double* omega_host,
-                   double* resid_host, nsf_stats* stats, int* wave_size);
+                   double* resid_host, nsf_stats* stats, nsf_c128* const* Y_dev,
+                   int* wave_size);
 void nsf_batch_destroy(nsf_batch batch);
 /*
  * nsf_plan_autotune on the first instance of every distinct grid shape (its

@@ -466,8 +466,38 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
   for (Group& G : groups)
     if ((rc = upload_descs(G, s))) return fail(rc);
 
-  // start vectors: seeded complex normal, A_r-normalised
-  for (Run* r : runs) NSF_HIP(r->p, launch_randn(r->w, r->len, r->seed, s));
+  // start vectors: seeded complex normal, A_r-normalised; with a start block Y0
+  // (nsf_eigs_set_start) a seeded combination sum_j c_j Y0_j, c_j complex normal,
+  // plus the normal vector at 1e-3 of its size, so that no direction is absent
+  for (Run* r : runs) {
+    nsf_plan p = r->p;
+    NSF_HIP(p, launch_randn(r->w, r->len, r->seed, s));
+    if (p->start_Y && p->start_count > 0) {
+      const int c = p->start_count;
+      // ||Y0_j||_2 is O(1) for A_r-normalised vectors, the normal vector's is sqrt(2 len)
+      const double tau = 1e-3 * std::sqrt((double)c / (2.0 * (double)r->len));
+      NSF_HIP(p, launch_scale_copy(r->w, r->w, tau, 0.0, r->len, s));
+      unsigned long long z = r->seed ^ 0x9e3779b97f4a7c15ULL;
+      auto u01 = [&z]() {
+        z += 0x9E3779B97F4A7C15ULL;
+        unsigned long long t = z;
+        t = (t ^ (t >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        t = (t ^ (t >> 27)) * 0x94D049BB133111EBULL;
+        t ^= t >> 31;
+        return ((t >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+      };
+      double2* hc = p->h_res + 64;
+      for (int j = 0; j < c; ++j) {  // -c_j, Box-Muller (multi_axpy subtracts)
+        const double a = std::sqrt(-2.0 * std::log(u01())), b = 6.283185307179586 * u01();
+        hc[j] = make_double2(-a * std::cos(b), -a * std::sin(b));
+      }
+      NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * c, hipMemcpyHostToDevice, s));
+      NSF_HIP(p, launch_multi_axpy(p->start_Y, r->len, c, p->d_coef, r->w, r->len, s));
+      NSF_HIP(p, hipStreamSynchronize(s));  // hc is reused below
+    }
+    p->start_Y = nullptr;  // used once
+    p->start_count = 0;
+  }
   if ((rc = apply_all(groups, s))) return fail(rc);
   for (Run* r : runs) {
     r->st.matvecs += 1;
@@ -482,13 +512,19 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
     r->nb = 1;
   }
 
+  using clk = std::chrono::steady_clock;
+  auto ms_since = [](clk::time_point t) { return std::chrono::duration<double, std::milli>(clk::now() - t).count(); };
+  double t_cg = 0, t_orth = 0, t_rst = 0;
   for (;;) {
     std::vector<Run*> act;
     for (Run* r : runs)
       if (!r->finished) act.push_back(r);
     if (act.empty()) break;
     // expand: w = A_r^{-1} B_r V[nb-1], z = A_r w
+    auto t0 = clk::now();
     if ((rc = cg_all(groups, act, s, &cg_graph))) return fail(rc);
+    t_cg += ms_since(t0);
+    t0 = clk::now();
     if ((rc = apply_all(groups, s))) return fail(rc);
     for (Run* r : act) {
       r->st.matvecs += 1;
@@ -522,6 +558,8 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
       r->nb += 1;
       r->st.lanczos_steps += 1;
     }
+    t_orth += ms_since(t0);
+    t0 = clk::now();
     bool any_restart = false;
     for (Run* r : act)
       if (r->nb == r->m + 1) {
@@ -539,6 +577,12 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
     if (changed)
       for (Group& G : groups)
         if ((rc = upload_descs(G, s))) return fail(rc);
+    t_rst += ms_since(t0);
+  }
+  for (Run* r : runs) {
+    r->st.ms_cg = t_cg;
+    r->st.ms_orth = t_orth;
+    r->st.ms_restart = t_rst;
   }
   release();
   return NSF_OK;
@@ -675,7 +719,9 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
   std::vector<Run*> runs{&r};
   rc = run_engine(runs, p->stream);
   if (rc) return rc;
+  const auto tr = std::chrono::steady_clock::now();
   if ((rc = refine_run(&r))) return rc;
+  r.st.ms_restart += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr).count();
   if (Y_dev)
     NSF_HIP(p, hipMemcpyAsync(Y_dev, r.V, sizeof(double2) * (size_t)nev * r.len, hipMemcpyDeviceToDevice, p->stream));
   NSF_HIP(p, hipStreamSynchronize(p->stream));
@@ -739,6 +785,15 @@ int nsf_batch_autotune(nsf_batch b, int reps, int* shapes_tuned) {
   return NSF_OK;
 }
 
+int nsf_eigs_set_start(nsf_plan p, const nsf_c128* Y0_dev, int count) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  if (count < 0 || count > 512 || (count > 0 && !Y0_dev))
+    return set_error(p, NSF_E_ARG, "start block: 0 <= count <= 512 device vectors");
+  p->start_Y = count ? reinterpret_cast<const double2*>(Y0_dev) : nullptr;
+  p->start_count = count;
+  return NSF_OK;
+}
+
 int nsf_batch_plan(nsf_batch b, int i, nsf_plan* plan) {
   if (!b || !plan || i < 0 || i >= (int)b->plans.size()) return set_error(nullptr, NSF_E_ARG, "bad batch index");
   *plan = b->plans[i];
@@ -747,7 +802,7 @@ int nsf_batch_plan(nsf_batch b, int i, nsf_plan* plan) {
 
 int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max_basis, int max_restarts,
                    unsigned long long seed, double* omega_host, double* resid_host, nsf_stats* stats,
-                   int* wave_size) {
+                   nsf_c128* const* Y_dev, int* wave_size) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!b || !omega_host) return set_error(nullptr, NSF_E_ARG, "NULL argument");
   const int B = (int)b->plans.size();
@@ -779,8 +834,12 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
     const int rc = run_engine(ptrs, b->stream);
     if (rc) return set_error(nullptr, rc, std::string("batch: ") + ptrs[0]->p->last_error);
     for (int i = w0; i < w1; ++i) {
-      const int rr = refine_run(&runs[i - w0]);
+      Run& r = runs[i - w0];
+      const int rr = refine_run(&r);
       if (rr) return set_error(nullptr, rr, "instance " + std::to_string(i) + ": " + b->plans[i]->last_error);
+      if (Y_dev && Y_dev[i])
+        NSF_HIP(r.p, hipMemcpyAsync(Y_dev[i], r.V, sizeof(double2) * (size_t)nev * r.len, hipMemcpyDeviceToDevice,
+                                    b->stream));
     }
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     for (int i = w0; i < w1; ++i) {

@@ -307,6 +307,10 @@ struct nsf_plan_s {
   double2* d_basis = nullptr;  // V and AV
   size_t basis_vectors = 0;    // capacity of V (and of AV)
 
+  // start block for the next eigensolve (nsf_eigs_set_start; caller-owned)
+  const double2* start_Y = nullptr;
+  int start_count = 0;
+
   // caller-provided workspace (nsf_plan_set_workspace): fields, CG vectors,
   // basis and small matrices are carved from it and never freed by the plan
   char* ws = nullptr;

@@ -47,7 +47,7 @@ EXPORTED = [
     "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
     "nsf_batch_create", "nsf_batch_plan", "nsf_batch_eigs", "nsf_batch_destroy",
     "nsf_plan_autotune", "nsf_batch_autotune", "nsf_plan_workspace_size", "nsf_plan_set_workspace",
-    "nsf_fields",
+    "nsf_fields", "nsf_eigs_set_start",
 ]
 
 
@@ -56,7 +56,8 @@ class nsf_stats(C.Structure):
                 ("cg_solves", C.c_int), ("lanczos_steps", C.c_int), ("restarts", C.c_int),
                 ("converged", C.c_int), ("ortho_passes", C.c_int), ("cg_iters_avg", C.c_double),
                 ("ms_total", C.c_double),
-                ("bytes_alg", C.c_double)]
+                ("bytes_alg", C.c_double), ("ms_cg", C.c_double), ("ms_orth", C.c_double),
+                ("ms_restart", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -124,11 +125,12 @@ def lib():
         "nsf_batch_create": (I, [C.POINTER(P), I, VP, VP, D, D, D, VP]),
         "nsf_batch_plan": (I, [P, I, C.POINTER(P)]),
         "nsf_batch_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, DP, C.POINTER(nsf_stats),
-                               C.POINTER(I)]),
+                               C.POINTER(C.c_void_p), C.POINTER(I)]),
         "nsf_batch_destroy": (None, [P]),
         "nsf_plan_autotune": (I, [P, I, C.POINTER(nsf_tune)]),
         "nsf_plan_workspace_size": (I, [P, I, I, C.POINTER(C.c_size_t)]),
         "nsf_fields": (I, [P, VP, VP]),
+        "nsf_eigs_set_start": (I, [P, VP, I]),
         "nsf_plan_set_workspace": (I, [P, VP, C.c_size_t]),
         "nsf_batch_autotune": (I, [P, I, C.POINTER(I)]),
         "nsf_status_string": (C.c_char_p, [I]),
@@ -340,17 +342,31 @@ def nsf_batch_plan(batch, i):
     return p
 
 
-def nsf_batch_eigs(batch, count, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, max_restarts=0, seed=0):
-    """Returns (status, omega[count, nev], resid[count, nev], list of stats dicts, wave size)."""
+def nsf_batch_eigs(batch, count, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, max_restarts=0, seed=0,
+                   Y=None):
+    """Returns (status, omega[count, nev], resid[count, nev], list of stats dicts, wave size).
+    Y: optional list of count device tensors (or None entries) of nev x 4n complex128."""
     omega = np.zeros((count, nev))
     resid = np.zeros((count, nev))
     st = (nsf_stats * count)()
     wave = C.c_int()
+    yp = None
+    if Y is not None:
+        yp = (C.c_void_p * count)(*[(_dptr(t, "c128").value if t is not None else None) for t in Y])
     status = _check(lib().nsf_batch_eigs(batch, int(nev), float(res_tol), float(cg_rtol), int(max_basis),
                                          int(max_restarts), C.c_ulonglong(seed),
                                          omega.ctypes.data_as(C.POINTER(C.c_double)),
-                                         resid.ctypes.data_as(C.POINTER(C.c_double)), st, C.byref(wave)))
+                                         resid.ctypes.data_as(C.POINTER(C.c_double)), st, yp, C.byref(wave)))
     return status, omega, resid, [x.as_dict() for x in st], wave.value
+
+
+def nsf_eigs_set_start(plan, Y0):
+    """Y0: device tensor of count x 4n complex128 (kept alive by the caller until the
+    next eigensolve returns), or None to clear."""
+    if Y0 is None:
+        return _check(lib().nsf_eigs_set_start(plan, None, 0), plan)
+    count = Y0.shape[0] if Y0.dim() == 2 else 1
+    return _check(lib().nsf_eigs_set_start(plan, _dptr(Y0, "c128"), int(count)), plan)
 
 
 def nsf_plan_autotune(plan, reps=10):
@@ -413,6 +429,11 @@ class Batch:
 
     def set_tensor(self, i, eps, mu, xi, zeta):
         return nsf_set_medium_tensor(self.plan(i), eps, mu, xi, zeta)
+
+    def set_start(self, i, Y0):
+        self._starts = getattr(self, "_starts", {})
+        self._starts[i] = Y0
+        return nsf_eigs_set_start(self.plan(i), Y0)
 
     def eigs(self, nev, **kw):
         return nsf_batch_eigs(self.handle, self.count, nev, **kw)
@@ -488,6 +509,10 @@ class Plan:
 
     def fields(self, y, eh):
         return nsf_fields(self.handle, y, eh)
+
+    def set_start(self, Y0):
+        self._start = Y0  # alive until the next eigensolve
+        return nsf_eigs_set_start(self.handle, Y0)
 
     def Br(self, u, out):
         return nsf_apply_Br(self.handle, u, out)

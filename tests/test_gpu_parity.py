@@ -628,3 +628,55 @@ def test_fields_of_eigenpairs_solve_the_gep_8():
             lhs = np.concatenate([C @ x[:3 * n], C.conj().T @ x[3 * n:]])
             rhsv = om[j] * (Bm @ x)
             assert np.linalg.norm(lhs - rhsv) <= 1e-9 * np.linalg.norm(rhsv)
+
+
+# ------------------------------------------------------------- warm starts
+
+def test_warm_start_from_neighbouring_k_same_eigenvalues_fewer_steps():
+    """Starting the Lanczos process from the Ritz vectors of a nearby Bloch vector
+    finds the same eigenvalues (1e-10) in fewer Lanczos steps; the start block is
+    used once."""
+    grid = (16, 16, 16)
+    eps, gam = media.sphere_chiral(16)
+    k0, k1 = (0.1, 0.2, 0.3), (0.12, 0.2, 0.3)
+    nev, n = 8, 16 ** 3
+    kw = dict(res_tol=1e-10, cg_rtol=1e-12, seed=4)
+    with nsf.Plan(grid, k0) as P:
+        P.set_chiral(eps, gam)
+        Y0 = torch.empty((nev, 4 * n), dtype=torch.complex128, device="cuda")
+        assert P.eigs(nev, Y=Y0, **kw)[0] == nsf.NSF_OK
+    with nsf.Plan(grid, k1) as P:
+        P.set_chiral(eps, gam)
+        st_c, om_c, _, s_c = P.eigs(nev, **kw)
+        P.set_start(Y0)
+        st_w, om_w, res_w, s_w = P.eigs(nev, **kw)
+        st_again, om_again, _, s_again = P.eigs(nev, **kw)  # block forgotten: cold again
+    assert st_c == st_w == st_again == nsf.NSF_OK
+    assert np.abs(om_w - om_c).max() <= 1e-10 * om_c.max()
+    assert s_w["lanczos_steps"] < s_c["lanczos_steps"]
+    assert s_again["lanczos_steps"] == s_c["lanczos_steps"]
+
+
+def test_batch_vectors_out_and_warm_start_in():
+    grids = [(16, 16, 16)] * 2 + [(8, 8, 8)]
+    ks = [(0.1, 0.2, 0.3), (0.3, 0.1, 0.2), (0.2, 0.2, 0.1)]
+    nev = 6
+    Ys = [torch.empty((nev, 4 * g[0] * g[1] * g[2]), dtype=torch.complex128, device="cuda") for g in grids]
+    with nsf.Batch(grids, ks) as B:
+        for i, g in enumerate(grids):
+            B.set_chiral(i, *media.sphere_chiral(*g))
+        st, om, res, stats, _ = B.eigs(nev, res_tol=1e-10, cg_rtol=1e-12, Y=Ys)
+        assert st == nsf.NSF_OK
+        for i in range(3):  # restart every instance from its own vectors
+            B.set_start(i, Ys[i])
+        st2, om2, res2, stats2, _ = B.eigs(nev, res_tol=1e-10, cg_rtol=1e-12)
+    assert st2 == nsf.NSF_OK
+    assert np.abs(om2 - om).max() <= 1e-10 * om.max()
+    assert all(b["lanczos_steps"] < a["lanczos_steps"] for a, b in zip(stats, stats2))
+    # the returned vectors are A_r-normalised eigenvectors of their instance's pencil
+    i, g = 2, grids[2]
+    eps, gam = media.sphere_chiral(*g)
+    tens = medium.tensors_chiral(eps, gam)
+    Yh = host(Ys[i])
+    for j in range(nev):
+        assert nfgep.pencil_residual(Yh[j], 1 / om[i, j], g, ks[i], tens) < 1e-9
