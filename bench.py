@@ -119,6 +119,62 @@ def batch_leg(name, log=sys.stderr):
             "grids": sorted(set(f"{g[0]}^3" for g in grids))}
 
 
+def kpath_warm_leg(log=sys.stderr, nev=10):
+    """The 40-point k-path of the 128^3 rods with warm starts: the plain loop starts
+    each k-point from the previous one's Ritz vectors; the batched schedule solves
+    the even-numbered k-points cold in one batch, then the odd-numbered ones in a
+    second batch, each started from its predecessor's vectors."""
+    import torch
+
+    from paper_1402_6297_amd import media, nsf
+
+    ks = media.kpath_gxmgr(10)
+    eps, gam = media.rods_pseudochiral(128)
+    g = (128, 128, 128)
+    n = 128 ** 3
+    kw = dict(res_tol=1e-8, cg_rtol=1e-10, seed=0)
+    t_plain, pairs_plain, steps_plain, prev = 0.0, 0, 0, None
+    for i, k in enumerate(ks):
+        with nsf.Plan(g, k) as P:
+            P.set_pseudochiral(0, 1, eps, gam)
+            Y = torch.empty((nev, 4 * n), dtype=torch.complex128, device="cuda")
+            if prev is not None:
+                P.set_start(prev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, om, res, stats = P.eigs(nev, Y=Y, **kw)
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
+            pairs_plain += stats["converged"]
+            steps_plain += stats["lanczos_steps"]
+            prev = Y
+    del prev, Y
+    print(f"[bench] kpath128 warm plain: {t_plain:.1f} s", file=log, flush=True)
+    even, odd = list(range(0, len(ks), 2)), list(range(1, len(ks), 2))
+    t_batch, pairs_batch, steps_batch = 0.0, 0, 0
+    Ye = [torch.empty((nev, 4 * n), dtype=torch.complex128, device="cuda") for _ in even]
+    for part, idx in (("even", even), ("odd", odd)):
+        with nsf.Batch([g] * len(idx), [ks[i] for i in idx]) as B:
+            for j, i in enumerate(idx):
+                B.set_pseudochiral(j, 0, 1, eps, gam)
+                if part == "odd":
+                    B.set_start(j, Ye[j])  # k-point i - 1 = even[j]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, om, res, stats, wave = B.eigs(nev, Y=Ye if part == "even" else None, **kw)
+            torch.cuda.synchronize()
+            t_batch += time.perf_counter() - t0
+        pairs_batch += sum(s["converged"] for s in stats)
+        steps_batch += sum(s["lanczos_steps"] for s in stats)
+    del Ye
+    print(f"[bench] kpath128 warm batched: {t_batch:.1f} s", file=log, flush=True)
+    return {"workload": "kpath128 with warm starts", "instances": len(ks), "nev": nev,
+            "eigenpairs_per_s_batched": round(pairs_batch / t_batch, 4),
+            "eigenpairs_per_s_plain": round(pairs_plain / t_plain, 4),
+            "s_batched": round(t_batch, 3), "s_plain": round(t_plain, 3),
+            "lanczos_steps_plain": steps_plain, "lanczos_steps_batched": steps_batch}
+
+
 def median_apply_us(P, u, out, reps=100, warm=10):
     """Median of `reps` individually timed A_r applies (HIP events on the plan's
     stream, which is torch's current stream), after `warm` untimed ones."""
@@ -352,8 +408,9 @@ def main():
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="only run this many A_r applies plus a 1 GiB device copy (for rocprofv3)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a rocprofv3 kernel-stats table and exit")
-    ap.add_argument("--batch", default="uneven6",
-                    help="batched-vs-plain leg after the steps: kpath128, uneven32, unevenN, or none")
+    ap.add_argument("--batch", default="uneven32",
+                    help="batched-vs-plain leg after the steps: kpath128, kpath128warm, uneven32, unevenN, "
+                         "or none")
     ap.add_argument("--grad", type=int, default=0, metavar="NVOX",
                     help="gradient leg at 64^3: kernel cost and central differences at NVOX voxels")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -491,7 +548,9 @@ def main():
     }
     if not args.no_extra:
         line["other_configs"] = extra_workloads()
-    if args.batch != "none":
+    if args.batch == "kpath128warm":
+        line["batch"] = kpath_warm_leg()
+    elif args.batch != "none":
         line["batch"] = batch_leg(args.batch)
     if args.grad:
         line["grad"] = grad_leg(args.grad)
