@@ -36,6 +36,9 @@ WORKLOADS = {
                     desc="pseudochiral x-y rods r=0.2 eps 13 gamma 0.4, 128^3, k=(0.1,0.2,0.3)"),
     "sphere64": dict(grid=(64, 64, 64), k=(0.25, 0.0, 0.0), kind="chiral",
                      desc="chiral sphere r=0.3 eps 13 gamma 0.5, 64^3, k=(0.25,0,0)"),
+    "scsc128": dict(grid=(128, 128, 128), k=(0.1, 0.2, 0.3), kind="scsc",
+                    desc="simple cubic spheres r=0.345 joined by cylinders s=0.11, (eps_i, eps_o, gamma) = "
+                         "(13, 1, 0.5), 128^3, k=(0.1,0.2,0.3)"),
 }
 
 
@@ -45,6 +48,8 @@ def make_medium(w):
     n1 = w["grid"][0]
     if w["kind"] == "chiral":
         return media.sphere_chiral(n1)
+    if w["kind"] == "scsc":
+        return media.spheres_cylinders_chiral(n1)
     return media.rods_pseudochiral(n1)
 
 
@@ -173,6 +178,33 @@ def kpath_warm_leg(log=sys.stderr, nev=10):
             "eigenpairs_per_s_plain": round(pairs_plain / t_plain, 4),
             "s_batched": round(t_batch, 3), "s_plain": round(t_plain, 3),
             "lanczos_steps_plain": steps_plain, "lanczos_steps_batched": steps_batch}
+
+
+def gamma_sweep_leg(n1=64, log=sys.stderr, nev=10):
+    """CG conditioning against the chirality (the paper's second test set): the
+    spheres-and-cylinders structure at k = (1/2, 0, 0), eps_i = 13 with gamma from
+    0.25 to 3 and eps_i = 1 with gamma from 0.05 to 0.9 (Phi -> 0 as gamma ->
+    sqrt(eps_i)).  Reports CG iterations per solve and the eigenvalues."""
+    import torch
+
+    from paper_1402_6297_amd import media, nsf
+
+    out = []
+    for eps_i, gammas in ((13.0, (0.25, 1.0, 2.0, 3.0)), (1.0, (0.05, 0.3, 0.6, 0.9))):
+        for gmm in gammas:
+            eps, gam = media.spheres_cylinders_chiral(n1, eps_in=eps_i, eps_out=1.0, gamma=gmm)
+            with nsf.Plan((n1, n1, n1), (0.5, 0.0, 0.0)) as P:
+                P.set_chiral(eps, gam)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, om, res, stats = P.eigs(nev, res_tol=1e-8, cg_rtol=1e-10)
+                torch.cuda.synchronize()
+                out.append({"eps_i": eps_i, "gamma": gmm, "status": st, "s": round(time.perf_counter() - t0, 3),
+                            "cg_iters_avg": round(stats["cg_iters_avg"], 2), "lanczos_steps": stats["lanczos_steps"],
+                            "omega": [round(x, 8) for x in om.tolist()], "max_residual": float(res.max())})
+            print(f"[bench] gamma sweep eps_i {eps_i} gamma {gmm}: cg avg {out[-1]['cg_iters_avg']}",
+                  file=log, flush=True)
+    return {"workload": f"spheres+cylinders {n1}^3, k=(0.5,0,0), nev={nev}", "points": out}
 
 
 def median_apply_us(P, u, out, reps=100, warm=10):
@@ -411,6 +443,7 @@ def main():
     ap.add_argument("--batch", default="uneven32",
                     help="batched-vs-plain leg after the steps: kpath128, kpath128warm, uneven32, unevenN, "
                          "or none")
+    ap.add_argument("--gamma-sweep", action="store_true", help="CG iterations against chirality (64^3)")
     ap.add_argument("--grad", type=int, default=0, metavar="NVOX",
                     help="gradient leg at 64^3: kernel cost and central differences at NVOX voxels")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -450,7 +483,7 @@ def main():
         P.set_option(nsf.NSF_OPT_MID_PAIRS, args.mid_pairs)
     dev_info = nsf.nsf_device_info(0)
     print(f"[bench] device {dev_info}", file=sys.stderr, flush=True)
-    if w["kind"] == "chiral":
+    if w["kind"] in ("chiral", "scsc"):
         P.set_chiral(eps, gam)
     else:
         P.set_pseudochiral(0, 1, eps, gam)
@@ -554,6 +587,8 @@ def main():
         line["batch"] = batch_leg(args.batch)
     if args.grad:
         line["grad"] = grad_leg(args.grad)
+    if args.gamma_sweep:
+        line["gamma_sweep"] = gamma_sweep_leg()
     if not args.no_cpu:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, eps, gam)

@@ -59,6 +59,28 @@ def sphere_chiral(n1, n2=None, n3=None, radius=0.3, centre=(0.5, 0.5, 0.5),
     return eps, gamma
 
 
+def spheres_cylinders_chiral(n1, n2=None, n3=None, radius=0.345, cyl_radius=0.11,
+                             eps_in=13.0, eps_out=1.0, gamma=0.5, a=1.0):
+    """The paper's simple cubic structure (Sec. 5): a sphere of radius r at every
+    lattice point, joined to its neighbours by circular cylinders of radius s along
+    the three lattice directions; inside the structure eps_in and chirality gamma,
+    outside eps_out and no chirality (the triplet (eps_i, eps_o, gamma)).
+    Voxel-centre indicator; the lattice point sits at the cell corner."""
+    n2 = n1 if n2 is None else n2
+    n3 = n1 if n3 is None else n3
+    X, Y, Z = voxel_centres(n1, n2, n3, a)
+    # offsets from the nearest lattice point (periodic images)
+    dx = X / a - np.round(X / a)
+    dy = Y / a - np.round(Y / a)
+    dz = Z / a - np.round(Z / a)
+    inside = dx ** 2 + dy ** 2 + dz ** 2 < radius ** 2
+    s2 = cyl_radius ** 2
+    inside |= (dy ** 2 + dz ** 2 < s2) | (dx ** 2 + dz ** 2 < s2) | (dx ** 2 + dy ** 2 < s2)
+    eps = np.where(inside, eps_in, eps_out).astype(np.float64)
+    gam = np.where(inside, gamma, 0.0).astype(np.float64)
+    return eps, gam
+
+
 def rods_pseudochiral(n1, n2=None, n3=None, radius=0.2, axis_xy=(0.5, 0.5),
                       eps_in=13.0, gamma_in=0.4, eps_out=1.0, gamma_out=0.0,
                       a=1.0):

@@ -680,3 +680,17 @@ def test_batch_vectors_out_and_warm_start_in():
     Yh = host(Ys[i])
     for j in range(nev):
         assert nfgep.pencil_residual(Yh[j], 1 / om[i, j], g, ks[i], tens) < 1e-9
+
+
+def test_paper_geometry_eigs_match_dense_8():
+    """The spheres-and-cylinders structure with (eps_i, eps_o, gamma) = (13, 1, 0.5)
+    at 8^3: the ten smallest omega against the dense pencil."""
+    grid, k = (8, 8, 8), (0.1, 0.2, 0.3)
+    eps, gam = media.spheres_cylinders_chiral(8)
+    om_all = nfgep.nfgep_dense(grid, k, medium.tensors_chiral(eps, gam))
+    ref = np.sort(om_all[om_all > 0])[:10]
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st, om, res, _ = P.eigs(10, res_tol=1e-10, cg_rtol=1e-12)
+    assert st == nsf.NSF_OK
+    assert np.abs(om - ref).max() < 1e-10 * ref.max()
