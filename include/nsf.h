@@ -113,9 +113,17 @@ enum {
   NSF_OPT_MID_PAIRS = 6, /* fused z pass of the two-level path: 1 one coupled
                             (E', H') field pair per workgroup (default), 0 all
                             six fields per workgroup                           */
-  NSF_OPT_CG_START = 7   /* eigensolver inner CG: 1 starts from the A_r-Galerkin
+  NSF_OPT_CG_START = 7,  /* eigensolver inner CG: 1 starts from the A_r-Galerkin
                             solution in the span of the Lanczos basis (default),
                             0 from zero; the Lanczos direction is the same     */
+  NSF_OPT_VERIFY = 8     /* nsf_eigs multiplicity checks, 0..16 (default 0): a
+                            single start vector finds one direction of a
+                            multiple eigenvalue only; each check restarts from a
+                            fresh random vector A_r-orthogonal to the converged
+                            pairs, keeps the best nev of the union, and stops
+                            when nothing changed.  Needed for spectra with
+                            multiple eigenvalues (symmetric media at symmetric
+                            k-points); not applied by nsf_batch_eigs           */
 };
 
 /*

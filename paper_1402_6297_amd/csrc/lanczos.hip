@@ -38,6 +38,7 @@ struct Run {
   int nb = 0;
   std::vector<double> theta, eta;
   double start_h2 = 0;  // |h|^2 of the projected CG start of the current step
+  int nlock = 0;        // V[0..nlock) (with A_r V) hold A_r-orthonormal vectors to keep
   std::vector<double2> Sk;
   nsf_stats st{};
   bool finished = false, converged = false;
@@ -424,6 +425,20 @@ int refresh_direction(Run* r, hipStream_t s) {
   return NSF_OK;
 }
 
+// H columns of the kept block V[0..nlock) (exact: B_r applied to each vector).
+int lock_in(Run* r, hipStream_t s) {
+  nsf_plan p = r->p;
+  for (int j = 0; j < r->nlock; ++j) {
+    NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, r->V + (size_t)j * r->len, r->bv, nullptr, s));
+    NSF_HIP(p, launch_multi_dot(r->V, r->len, j + 1, r->bv, r->len, p->d_partial, p->d_coef, s));
+    NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_coef, sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, s));
+    NSF_HIP(p, hipStreamSynchronize(s));
+    admit_finish(r, j);
+  }
+  r->nb = r->nlock;
+  return NSF_OK;
+}
+
 // Run every instance to convergence (or its restart cap) in lock step.
 int run_engine(std::vector<Run*>& runs, hipStream_t s) {
   // groups of equal grid shape and pass configuration
@@ -465,8 +480,13 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
   };
   for (Group& G : groups)
     if ((rc = upload_descs(G, s))) return fail(rc);
+  for (Run* r : runs) {
+    r->nb = 0;
+    if (r->nlock > 0 && (rc = lock_in(r, s))) return fail(rc);
+  }
 
-  // start vectors: seeded complex normal, A_r-normalised; with a start block Y0
+  // start vectors: seeded complex normal, A_r-normalised (and A_r-orthogonal to
+  // a kept block); with a start block Y0
   // (nsf_eigs_set_start) a seeded combination sum_j c_j Y0_j, c_j complex normal,
   // plus the normal vector at 1e-3 of its size, so that no direction is absent
   for (Run* r : runs) {
@@ -501,15 +521,17 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
   if ((rc = apply_all(groups, s))) return fail(rc);
   for (Run* r : runs) {
     r->st.matvecs += 1;
+    for (int pass = 0; pass < (r->nb > 0 ? 2 : 0); ++pass)
+      if ((rc = ortho_pass(r))) return fail(rc);
     if ((rc = dot_async(r->p, r->w, r->z, r->len, 0))) return fail(rc);
   }
   NSF_HIP(runs[0]->p, hipStreamSynchronize(s));
   for (Run* r : runs)
-    if ((rc = admit_enqueue(r, 0, r->p->h_res[0].x))) return fail(rc);
+    if ((rc = admit_enqueue(r, r->nb, r->p->h_res[0].x))) return fail(rc);
   NSF_HIP(runs[0]->p, hipStreamSynchronize(s));
   for (Run* r : runs) {
-    admit_finish(r, 0);
-    r->nb = 1;
+    admit_finish(r, r->nb);
+    r->nb += 1;
   }
 
   using clk = std::chrono::steady_clock;
@@ -666,14 +688,17 @@ int refine_run(Run* r) {
     if (!(r->theta[i] > 0.0) || !(r->eta[i] <= r->res_tol)) all = false;
   }
   r->converged = all;
-  // insertion sort by descending theta; columns move through the bv scratch
+  // insertion sort by descending theta; columns of V and A_r V move through
+  // the bv scratch
   for (int i = 1; i < r->nev; ++i)
     for (int j = i; j > 0 && r->theta[j] > r->theta[j - 1]; --j) {
-      double2* a0 = r->V + (size_t)(j - 1) * L;
-      double2* a1 = r->V + (size_t)j * L;
-      NSF_HIP(p, hipMemcpyAsync(r->bv, a0, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
-      NSF_HIP(p, hipMemcpyAsync(a0, a1, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
-      NSF_HIP(p, hipMemcpyAsync(a1, r->bv, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
+      for (double2* M : {r->V, r->AV}) {
+        double2* a0 = M + (size_t)(j - 1) * L;
+        double2* a1 = M + (size_t)j * L;
+        NSF_HIP(p, hipMemcpyAsync(r->bv, a0, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
+        NSF_HIP(p, hipMemcpyAsync(a0, a1, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
+        NSF_HIP(p, hipMemcpyAsync(a1, r->bv, sizeof(double2) * L, hipMemcpyDeviceToDevice, s));
+      }
       std::swap(r->theta[j], r->theta[j - 1]);
       std::swap(r->eta[j], r->eta[j - 1]);
     }
@@ -719,9 +744,42 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
   std::vector<Run*> runs{&r};
   rc = run_engine(runs, p->stream);
   if (rc) return rc;
-  const auto tr = std::chrono::steady_clock::now();
+  auto tr = std::chrono::steady_clock::now();
   if ((rc = refine_run(&r))) return rc;
   r.st.ms_restart += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr).count();
+  // Multiplicity check: a single start vector cannot see more than one direction
+  // of a multiple eigenvalue.  Each check keeps the converged vectors, starts a
+  // new Lanczos sequence from a fresh random vector A_r-orthogonal to them, and
+  // takes the best nev pairs of the union; it stops once a check changes nothing.
+  for (int v = 0; v < p->opt_verify; ++v) {
+    std::vector<double> before(r.theta.begin(), r.theta.begin() + nev);
+    Run r2;
+    if ((rc = make_run(p, nev, res_tol, cg_rtol, max_basis, max_restarts, seed + 7919ULL * (v + 1), r2)))
+      return rc;
+    r2.nlock = nev;
+    const nsf_stats acc = r.st;
+    runs[0] = &r2;
+    if ((rc = run_engine(runs, p->stream))) return rc;
+    tr = std::chrono::steady_clock::now();
+    if ((rc = refine_run(&r2))) return rc;
+    r2.st.ms_restart += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr).count();
+    bool changed = false;
+    for (int i = 0; i < nev; ++i)
+      changed |= std::fabs(r2.theta[i] - before[i]) > 1e-10 * std::fabs(before[0]);
+    const nsf_stats add = r2.st;
+    r = std::move(r2);
+    r.st = acc;  // counters of every sequence add up
+    r.st.matvecs += add.matvecs;
+    r.st.cg_iters_total += add.cg_iters_total;
+    r.st.cg_solves += add.cg_solves;
+    r.st.lanczos_steps += add.lanczos_steps;
+    r.st.restarts += add.restarts;
+    r.st.ortho_passes += add.ortho_passes;
+    r.st.ms_cg += add.ms_cg;
+    r.st.ms_orth += add.ms_orth;
+    r.st.ms_restart += add.ms_restart;
+    if (!changed) break;
+  }
   if (Y_dev)
     NSF_HIP(p, hipMemcpyAsync(Y_dev, r.V, sizeof(double2) * (size_t)nev * r.len, hipMemcpyDeviceToDevice, p->stream));
   NSF_HIP(p, hipStreamSynchronize(p->stream));

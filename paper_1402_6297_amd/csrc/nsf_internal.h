@@ -321,6 +321,7 @@ struct nsf_plan_s {
   int opt_mid_cols = 16;    // pencils per workgroup of the fused z pass
   int opt_cg_graph = 1;     // CG iterations of the eigensolver replayed from a HIP graph
   int opt_cg_start = 1;     // eigensolver CG starts from the Galerkin solution in span(V)
+  int opt_verify = 0;       // multiplicity checks after convergence (nsf_eigs)
 
   std::string last_error;
 };

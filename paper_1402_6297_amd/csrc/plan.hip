@@ -375,6 +375,10 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_START takes 0 or 1");
       p->opt_cg_start = value;
       return NSF_OK;
+    case NSF_OPT_VERIFY:
+      if (value < 0 || value > 16) return set_error(p, NSF_E_ARG, "NSF_OPT_VERIFY takes 0..16");
+      p->opt_verify = value;
+      return NSF_OK;
     case NSF_OPT_CG_GRAPH:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_GRAPH takes 0 or 1");
       p->opt_cg_graph = value;

@@ -694,3 +694,64 @@ def test_paper_geometry_eigs_match_dense_8():
         st, om, res, _ = P.eigs(10, res_tol=1e-10, cg_rtol=1e-12)
     assert st == nsf.NSF_OK
     assert np.abs(om - ref).max() < 1e-10 * ref.max()
+
+
+# ------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("grid,k", [((512, 4, 6), (0.2, 0.1, 0.3)), ((256, 8, 8), (0.1, 0.3, 0.2)),
+                                    ((6, 512, 4), (0.4, 0.1, 0.1))])
+def test_Ar_longest_axes(grid, k):
+    """The longest axes the plan accepts (512, generic Stockham passes; 256, register passes)."""
+    n = grid[0] * grid[1] * grid[2]
+    eps, gam, tens, pair = _medium("noise", grid)
+    u = media.random_vector(4 * n, 13)
+    with nsf.Plan(grid, k) as P:
+        _set(P, eps, gam, pair)
+        out = torch.empty(4 * n, dtype=torch.complex128, device="cuda")
+        P.Ar(dev(u), out)
+        assert rel(host(out), nfgep.apply_Ar(u, grid, k, tens)) < 1e-12
+
+
+def test_eigs_degenerate_spectrum_air():
+    """Air at k on a lattice axis: each omega = sigma_f occurs twice (two polarisations)
+    and the frequencies of the (0, +-1) and (0, 0, +-1) neighbours coincide; the
+    solver returns every copy."""
+    grid, k = (8, 8, 8), (0.1, 0.0, 0.0)
+    eps, gam = media.homogeneous(8, eps=1.0, gamma=0.0)
+    L1, L2, L3 = yee.lambdas(grid, k)
+    sig = np.sqrt(np.abs(L1) ** 2 + np.abs(L2) ** 2 + np.abs(L3) ** 2)
+    ref = np.sort(np.concatenate([sig, sig]))[:12]
+    assert np.sum(np.isclose(ref, ref[0], rtol=1e-12)) >= 2  # degenerate indeed
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        P.set_option(nsf.NSF_OPT_VERIFY, 16)
+        st, om, res, stats = P.eigs(12, res_tol=1e-10, cg_rtol=1e-12)
+    assert st == nsf.NSF_OK
+    assert np.abs(om - ref).max() < 1e-10 * ref.max()
+
+
+def test_multiplicity_checks_leave_a_simple_spectrum_alone():
+    """On a spectrum without multiple eigenvalues one check confirms the result."""
+    grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
+    eps, gam = media.sphere_chiral(16)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st0, om0, _, s0 = P.eigs(6, res_tol=1e-10, cg_rtol=1e-12, seed=1)
+        P.set_option(nsf.NSF_OPT_VERIFY, 3)
+        st1, om1, res1, s1 = P.eigs(6, res_tol=1e-10, cg_rtol=1e-12, seed=1)
+    assert st0 == st1 == nsf.NSF_OK and res1.max() <= 1e-10
+    assert np.abs(om1 - om0).max() <= 1e-10 * om0.max()
+    assert s1["lanczos_steps"] > s0["lanczos_steps"]  # one check ran and changed nothing
+
+
+def test_eigs_rejects_bad_arguments():
+    with nsf.Plan((4, 4, 4), (0.1, 0.2, 0.3)) as P:
+        with pytest.raises(nsf.NsfError) as e:
+            P.eigs(2)  # no medium yet
+        assert e.value.status == nsf.NSF_E_STATE
+        P.set_chiral(*media.sphere_chiral(4))
+        for bad in (dict(nev=0), dict(nev=128), dict(nev=2, res_tol=0.0), dict(nev=2, cg_rtol=-1.0)):
+            nev = bad.pop("nev")
+            with pytest.raises(nsf.NsfError) as e:
+                P.eigs(nev, **bad)
+            assert e.value.status == nsf.NSF_E_ARG
