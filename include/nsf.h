@@ -116,7 +116,7 @@ enum {
   NSF_OPT_CG_START = 7,  /* eigensolver inner CG: 1 starts from the A_r-Galerkin
                             solution in the span of the Lanczos basis (default),
                             0 from zero; the Lanczos direction is the same     */
-  NSF_OPT_VERIFY = 8     /* nsf_eigs multiplicity checks, 0..16 (default 0): a
+  NSF_OPT_VERIFY = 8,    /* nsf_eigs multiplicity checks, 0..16 (default 0): a
                             single start vector finds one direction of a
                             multiple eigenvalue only; each check restarts from a
                             fresh random vector A_r-orthogonal to the converged
@@ -124,10 +124,17 @@ enum {
                             when nothing changed.  Needed for spectra with
                             multiple eigenvalues (symmetric media at symmetric
                             k-points); not applied by nsf_batch_eigs           */
+  NSF_OPT_ORTHO_GATE = 9 /* eigensolver Gram-Schmidt: 1 skips the basis update
+                            of a new Lanczos direction on the device when its
+                            A_r-cosine with every basis vector is at most
+                            1e-2 res_tol, capped at 1e-10 (default), 0 always
+                            applies it; converged pairs meet the residual
+                            tolerance either way                             */
 };
 
 /*
- * Set a tuning option.  Options change speed, never results beyond rounding.
+ * Set a tuning option.  Options change speed: the tilings change results by
+ * rounding only, the eigensolver options within the requested tolerances.
  * Host-only.  NSF_E_ARG for an unknown option or value.
  */
 int nsf_plan_set_option(nsf_plan plan, int option, int value);

@@ -304,12 +304,23 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
   return NSF_OK;
 }
 
-// Gram-Schmidt pass of (w, z) against V[0..nb) in the A_r inner product.
-int ortho_pass(Run* r) {
+// A_r-cosine between w and every basis vector below which a gated
+// Gram-Schmidt pass leaves (w, z) as they are: 1e-2 of the residual tolerance,
+// at most 1e-10.  After the projected CG start the new direction is already
+// A_r-orthogonal to the basis to about the CG tolerance; a basis that is
+// orthogonal to level c only reaches residuals of about c, hence the margin.
+double ortho_skip_cos(const Run* r) { return std::min(1e-10, 1e-2 * r->res_tol); }
+
+// Gram-Schmidt pass of (w, z) against V[0..nb) in the A_r inner product.  With
+// gate_slot >= 0, d_res[gate_slot] holds ||w||_A^2 and the update is skipped on
+// the device when every coefficient is below ortho_skip_cos ||w||_A.
+int ortho_pass(Run* r, int gate_slot = -1) {
   nsf_plan p = r->p;
   hipStream_t s = p->stream;
+  const double c = ortho_skip_cos(r);
   NSF_HIP(p, launch_multi_dot(r->AV, r->len, r->nb, r->w, r->len, p->d_partial, p->d_coef, s));
-  NSF_HIP(p, launch_multi_axpy(r->V, r->len, r->nb, p->d_coef, r->w, r->len, s, r->AV, r->z));
+  NSF_HIP(p, launch_multi_axpy(r->V, r->len, r->nb, p->d_coef, r->w, r->len, s, r->AV, r->z,
+                               gate_slot >= 0 ? p->d_res + gate_slot : nullptr, c * c));
   r->st.ortho_passes += 1;
   return dot_async(p, r->w, r->z, r->len, 1);
 }
@@ -551,7 +562,7 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
     for (Run* r : act) {
       r->st.matvecs += 1;
       if ((rc = dot_async(r->p, r->w, r->z, r->len, 0))) return fail(rc);  // norm before
-      if ((rc = ortho_pass(r))) return fail(rc);
+      if ((rc = ortho_pass(r, r->p->opt_ortho_gate ? 0 : -1))) return fail(rc);
     }
     NSF_HIP(act[0]->p, hipStreamSynchronize(s));
     bool again = false;

@@ -238,10 +238,12 @@ hipError_t launch_cg_p(double2* p, const double2* r, long long len, CgState* st,
 // c[i] = sum_e conj(V_i[e]) w[e], i < m, written as m complex values to out.
 hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2* w, long long len,
                             double2* partial, double2* out, hipStream_t s);
-// w -= sum_i c[i] V_i and, if V2 is given, z -= sum_i c[i] V2_i  (c on device, m <= 512)
+// w -= sum_i c[i] V_i and, if V2 is given, z -= sum_i c[i] V2_i  (c on device, m <= 512).
+// With a gate (device, ||w||^2 in gate->x) nothing is written when
+// max_i |c[i]|^2 <= tau2 ||w||^2.
 hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
                              long long len, hipStream_t s, const double2* V2 = nullptr,
-                             double2* z = nullptr);
+                             double2* z = nullptr, const double2* gate = nullptr, double tau2 = 0.0);
 // V[:, 0:k] = V[:, 0:m] S (S device, m x k column-major complex), in place.
 hipError_t launch_rotate(double2* V, long long ld, int m, int k, const double2* S, long long len,
                          hipStream_t s);
@@ -322,6 +324,7 @@ struct nsf_plan_s {
   int opt_cg_graph = 1;     // CG iterations of the eigensolver replayed from a HIP graph
   int opt_cg_start = 1;     // eigensolver CG starts from the Galerkin solution in span(V)
   int opt_verify = 0;       // multiplicity checks after convergence (nsf_eigs)
+  int opt_ortho_gate = 1;   // skip negligible Gram-Schmidt updates on the device
 
   std::string last_error;
 };

@@ -39,6 +39,7 @@ NSF_OPT_YZ_COLS = 5
 NSF_OPT_MID_PAIRS = 6
 NSF_OPT_CG_START = 7
 NSF_OPT_VERIFY = 8
+NSF_OPT_ORTHO_GATE = 9
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",

@@ -107,6 +107,7 @@ def test_status_strings():
     (nsf.NSF_OPT_MID_PAIRS, [0, 1], [-1, 2]),
     (nsf.NSF_OPT_CG_START, [0, 1], [-1, 2]),
     (nsf.NSF_OPT_VERIFY, [0, 1, 16], [-1, 17]),
+    (nsf.NSF_OPT_ORTHO_GATE, [0, 1], [-1, 2]),
 ])
 def test_plan_options_validate(option, good, bad):
     p = nsf.nsf_plan_create(8, 8, 8, 1.0, (0.1, 0.2, 0.3), stream=0)

@@ -496,6 +496,30 @@ def test_projected_cg_start_same_eigenpairs(batched):
     assert it1 < it0
 
 
+@pytest.mark.parametrize("res_tol", [1e-8, 1e-11])
+@pytest.mark.parametrize("batched", [False, True], ids=["single", "batch"])
+def test_ortho_gate_same_eigenpairs(batched, res_tol):
+    """Skipping a Gram-Schmidt update whose coefficients are all below
+    min(1e-10, 1e-2 res_tol) ||w||_A leaves the converged pairs within the
+    tolerance: both runs converge to res_tol and agree on omega to max(1e-10,
+    10 res_tol^2)-level (the Rayleigh quotients are second order in the vector
+    error)."""
+    grids = [(32, 32, 32), (16, 16, 16), (24, 8, 16)] if batched else [(32, 32, 32)]
+    ks = [(0.1, 0.2, 0.3), (0.3, 0.1, 0.2), (0.2, 0.2, 0.1)][:len(grids)]
+    out = []
+    for gate in (0, 1):
+        with nsf.Batch(grids, ks) as B:
+            for i, g in enumerate(grids):
+                B.set_chiral(i, *media.sphere_chiral(*g))
+                nsf.nsf_plan_set_option(B.plan(i), nsf.NSF_OPT_ORTHO_GATE, gate)
+            st, om, res, stats, _ = B.eigs(6, res_tol=res_tol, cg_rtol=min(1e-10, 1e-2 * res_tol), seed=2)
+            out.append((st, om, res))
+    (s0, om0, r0), (s1, om1, r1) = out
+    assert s0 == s1 == nsf.NSF_OK
+    assert r0.max() <= res_tol and r1.max() <= res_tol
+    assert np.abs(om1 - om0).max() <= 1e-10 * om0.max()
+
+
 # ------------------------------------------------------------ general media
 
 GENERAL_CASES = [((4, 4, 4), (0.1, 0.2, 0.3)), ((16, 12, 10), (0.3, 0.1, 0.2)),
