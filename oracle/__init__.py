@@ -18,6 +18,9 @@ It computes, slowly and literally, what the paper defines:
                discrete GEP (Sec. 3), plain CG (Sec. 4.2) and eigenvalues by
                dense LAPACK, by ARPACK on the pencil, and by sparse
                shift-invert on the 6n GEP.
+* ``nfsep``  -- the null space free eigenvalue problem K y = omega y for any
+               medium with a nonsingular B (Thm 3.2): K dense and matrix-free,
+               GMRES, and shift-and-invert Arnoldi at zero shift (Sec. 4).
 * ``grad``   -- eigenvalue derivatives w.r.t. per-voxel eps and gamma from the
                left/right eigenvectors of the GEP.
 

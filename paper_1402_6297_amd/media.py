@@ -28,6 +28,9 @@ __all__ = [
     "uneven_batch",
     "random_vector",
     "homogeneous",
+    "lossy_sphere_tensors",
+    "random_nonhhpd",
+    "homogeneous_tensors",
 ]
 
 
@@ -153,6 +156,77 @@ def random_general(n1, n2=None, n3=None, seed=0, xi_norm=0.6):
     eps = 0.5 * (eps + np.conj(np.transpose(eps, (0, 2, 1))))
     mu = 0.5 * (mu + np.conj(np.transpose(mu, (0, 2, 1))))
     return eps, mu, xi, np.ascontiguousarray(zeta)
+
+
+def _iso(values, n):
+    """(n,) complex scalars -> (n, 3, 3) isotropic tensors value * I."""
+    return np.asarray(values, dtype=np.complex128).reshape(n)[:, None, None] * np.eye(3)[None]
+
+
+def lossy_sphere_tensors(n1, n2=None, n3=None, radius=0.3, eps_in=13.0 + 0.5j, gamma_in=0.5,
+                         eps_out=1.0, a=1.0):
+    """Lossy chiral sphere as per-voxel tensors (eps, mu, xi, zeta), each (n, 3, 3) complex.
+
+    Inside: eps = eps_in I with a positive imaginary part (absorption), xi =
+    i gamma_in I, zeta = -i gamma_in I; outside: eps_out I, no chirality; mu = I.
+    The complex permittivity makes eps_d, and hence Phi, non-Hermitian, so the
+    medium lies outside the Hermitian positive definite assumption (Sec. 4.1)
+    while B stays nonsingular (Sec. 3).
+    """
+    n2 = n1 if n2 is None else n2
+    n3 = n1 if n3 is None else n3
+    n = n1 * n2 * n3
+    X, Y, Z = voxel_centres(n1, n2, n3, a)
+    inside = ((X - 0.5 * a) ** 2 + (Y - 0.5 * a) ** 2 + (Z - 0.5 * a) ** 2 < (radius * a) ** 2).ravel()
+    eps = np.where(inside, eps_in, eps_out)
+    gam = np.where(inside, gamma_in, 0.0)
+    return _iso(eps, n), _iso(np.ones(n), n), _iso(1j * gam, n), _iso(-1j * gam, n)
+
+
+def random_nonhhpd(n1, n2=None, n3=None, seed=0, loss=0.4, coupling=0.4):
+    """Random bianisotropic voxel tensors with no Hermitian structure, each (n, 3, 3).
+
+    eps = R diag(e) R^* + i loss G_e G_e^* (e ~ U[2, 12], G_e complex normal /
+    sqrt 3), mu = Q diag(d) Q^* with d ~ U[0.8, 1.4] (Q, R random unitary), and
+    xi, zeta two independent complex normal matrices of spectral norm coupling,
+    so zeta != xi^* (a non-reciprocal lossy medium, Sec. 3: the NFSEP needs only
+    a nonsingular B).
+    """
+    n2 = n1 if n2 is None else n2
+    n3 = n1 if n3 is None else n3
+    n = n1 * n2 * n3
+    rng = np.random.default_rng(seed)
+
+    def cnormal():
+        return rng.standard_normal((n, 3, 3)) + 1j * rng.standard_normal((n, 3, 3))
+
+    def unitary():
+        q, _ = np.linalg.qr(cnormal())
+        return q
+
+    def herm(vals, q):
+        return np.einsum("gij,gj,gkj->gik", q, vals, q.conj())
+
+    ge = cnormal() / np.sqrt(3.0)
+    eps = herm(rng.uniform(2.0, 12.0, (n, 3)), unitary()) + 1j * loss * np.einsum("gij,gkj->gik", ge, ge.conj())
+    mu = herm(rng.uniform(0.8, 1.4, (n, 3)), unitary())
+    mu = 0.5 * (mu + np.conj(np.transpose(mu, (0, 2, 1))))
+
+    def scaled():
+        a = cnormal()
+        return a * (coupling / np.linalg.norm(a, ord=2, axis=(1, 2)))[:, None, None]
+
+    xi = scaled()
+    zeta = scaled()
+    return eps, mu, xi, zeta
+
+
+def homogeneous_tensors(n1, n2=None, n3=None, *, eps=1.0, mu=1.0, xi=0.0, zeta=0.0):
+    """Constant isotropic tensors eps I, mu I, xi I, zeta I (complex scalars allowed)."""
+    n2 = n1 if n2 is None else n2
+    n3 = n1 if n3 is None else n3
+    n = n1 * n2 * n3
+    return tuple(_iso(np.full(n, v, dtype=np.complex128), n) for v in (eps, mu, xi, zeta))
 
 
 def homogeneous(n1, n2=None, n3=None, *, eps=1.0, gamma=0.0):
