@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SVD-FFT matvec GB/s at 128^3; eigenpairs/s batched vs plain at res≤1e-8"
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_APPLY_PER_N = 336  # y in (64n) + 6 fields out (96n) + in (96n) + medium (16n) + out (64n)
+NFSEP_FIELD_BYTES_PER_N = 320  # the same field traffic; the NFSEP medium adds 576 B (per voxel) or 2 B (palette)
 
 WORKLOADS = {
     "sphere128": dict(grid=(128, 128, 128), k=(0.1, 0.2, 0.3), kind="chiral",
@@ -205,6 +206,64 @@ def gamma_sweep_leg(n1=64, log=sys.stderr, nev=10):
             print(f"[bench] gamma sweep eps_i {eps_i} gamma {gmm}: cg avg {out[-1]['cg_iters_avg']}",
                   file=log, flush=True)
     return {"workload": f"spheres+cylinders {n1}^3, k=(0.5,0,0), nev={nev}", "points": out}
+
+
+def nfsep_leg(n1=64, log=sys.stderr, nev=10):
+    """The NFSEP path (Thm 3.2; Algorithm 1, else-branch) on a lossy chiral sphere
+    (eps_in = 13 + 0.5i, gamma 0.5, r = 0.3) at n1^3, k = (0.1, 0.2, 0.3), a medium
+    outside the HHPD assumption: median K apply and median Kern apply (the A_r
+    pipeline with the full 6x6 factor, 896 n B algorithmic), and one zero-shift
+    shift-invert Arnoldi eigensolve (nev, residual <= 1e-8, GMRES rtol 1e-10)."""
+    import torch
+
+    from paper_1402_6297_amd import media, nsf
+
+    grid, k = (n1, n1, n1), (0.1, 0.2, 0.3)
+    n = n1 ** 3
+    tens = media.lossy_sphere_tensors(n1)
+    u = torch.from_numpy(media.random_vector(4 * n, 0)).to("cuda")
+    o = torch.empty_like(u)
+    with nsf.Plan(grid, k) as P:  # factors stored per voxel, for comparison
+        P.set_option(nsf.NSF_OPT_MEDIUM_PALETTE, 0)
+        P.set_nfsep(*tens)
+        kern_full_us = median_apply_us(P, u, o)
+    with nsf.Plan(grid, k) as P:
+        P.set_nfsep(*tens)
+        info = P.medium_info()
+        kern_us = median_apply_us(P, u, o)
+        for _ in range(5):
+            P.K(u, o)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+        for a, b in ev:
+            a.record()
+            P.K(u, o)
+            b.record()
+        torch.cuda.synchronize()
+        k_us = float(np.median([a.elapsed_time(b) * 1e3 for a, b in ev]))
+        del u, o
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, om, res, stats = P.eigs_nfsep(nev, res_tol=1e-8, inner_rtol=1e-10)
+        dt = time.perf_counter() - t0
+    b = (NFSEP_FIELD_BYTES_PER_N + info["voxel_bytes"]) * n
+    b_full = (NFSEP_FIELD_BYTES_PER_N + 576) * n
+    out = {"workload": f"lossy chiral sphere {n1}^3 (eps 13+0.5i, gamma 0.5), k=(0.1,0.2,0.3), nev={nev}",
+           "palette": info["palette"], "bytes_alg_per_apply": b,
+           "kern_apply_us": round(kern_us, 2), "kern_GBps_alg": round(b / (kern_us * 1e-6) / 1e9, 2),
+           "kern_frac": round(b / (kern_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+           "kern_per_voxel_factors_us": round(kern_full_us, 2),
+           "kern_per_voxel_factors_GBps_alg": round(b_full / (kern_full_us * 1e-6) / 1e9, 2),
+           "K_apply_us": round(k_us, 2),
+           "eigs_status": st, "s_per_solve": round(dt, 3),
+           "omega": [[round(w.real, 10), round(w.imag, 10)] for w in om],
+           "max_residual": float(res.max()), "applies": stats["matvecs"],
+           "gmres_iters_avg": round(stats["cg_iters_avg"], 2), "arnoldi_steps": stats["lanczos_steps"],
+           "restarts": stats["restarts"], "value_GBps": round(b * stats["matvecs"] / dt / 1e9, 2),
+           "ms_phases": {"gmres": round(stats["ms_cg"], 1), "gram_schmidt": round(stats["ms_orth"], 1),
+                         "restart_refine": round(stats["ms_restart"], 1)}}
+    print(f"[bench] nfsep {n1}^3: {out['s_per_solve']} s, {out['applies']} applies, "
+          f"kern apply {out['kern_apply_us']} us", file=log, flush=True)
+    return out
 
 
 def median_apply_us(P, u, out, reps=100, warm=10):
@@ -444,6 +503,8 @@ def main():
                     help="batched-vs-plain leg after the steps: kpath128, kpath128warm, uneven32, unevenN, "
                          "or none")
     ap.add_argument("--gamma-sweep", action="store_true", help="CG iterations against chirality (64^3)")
+    ap.add_argument("--nfsep", type=int, default=64, metavar="N",
+                    help="NFSEP leg (lossy sphere, shift-invert Arnoldi) at N^3; 0 skips it")
     ap.add_argument("--grad", type=int, default=0, metavar="NVOX",
                     help="gradient leg at 64^3: kernel cost and central differences at NVOX voxels")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -589,6 +650,8 @@ def main():
         line["grad"] = grad_leg(args.grad)
     if args.gamma_sweep:
         line["gamma_sweep"] = gamma_sweep_leg()
+    if args.nfsep:
+        line["nfsep"] = nfsep_leg(args.nfsep)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, eps, gam)

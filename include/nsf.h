@@ -74,7 +74,8 @@ enum {
 };
 
 /* Medium kinds reported by nsf_plan_query. */
-enum { NSF_MEDIUM_NONE = 0, NSF_MEDIUM_CHIRAL = 1, NSF_MEDIUM_PSEUDOCHIRAL = 2, NSF_MEDIUM_GENERAL = 3 };
+enum { NSF_MEDIUM_NONE = 0, NSF_MEDIUM_CHIRAL = 1, NSF_MEDIUM_PSEUDOCHIRAL = 2, NSF_MEDIUM_GENERAL = 3,
+       NSF_MEDIUM_NFSEP = 4 };
 
 /*
  * Create a plan for one Bloch vector on an n1 x n2 x n3 Yee grid of the simple
@@ -124,13 +125,30 @@ enum {
                             when nothing changed.  Needed for spectra with
                             multiple eigenvalues (symmetric media at symmetric
                             k-points); not applied by nsf_batch_eigs           */
-  NSF_OPT_ORTHO_GATE = 9 /* eigensolver Gram-Schmidt: 1 skips the basis update
+  NSF_OPT_ORTHO_GATE = 9, /* eigensolver Gram-Schmidt: 1 skips the basis update
                             of a new Lanczos direction on the device when its
                             A_r-cosine with every basis vector is at most
                             1e-2 res_tol, capped at 1e-10 (default), 0 always
                             applies it; converged pairs meet the residual
                             tolerance either way                             */
+  NSF_OPT_GMRES_RESTART = 10, /* restart length of the GMRES inner solves of
+                            nsf_eigs_nfsep, 4..500 (default 40)             */
+  NSF_OPT_MEDIUM_PALETTE = 11 /* general and NFSEP media, read by the next
+                            nsf_set_medium_tensor / nsf_set_medium_nfsep: 1
+                            stores the distinct voxel factors once plus a
+                            16-bit index per voxel when there are at most
+                            4096 of them (default; piecewise-constant media),
+                            0 always stores one factor per voxel           */
 };
+
+/*
+ * Device bytes per voxel that an A_r / Kern apply reads for the medium: 16
+ * for chiral and pseudochiral media ((eps, gamma)), 336 (general) or 576
+ * (NFSEP) for factors stored per voxel, 2 with a palette; palette (nullable)
+ * receives the number of distinct voxel factors, 0 when stored per voxel or
+ * for chiral / pseudochiral media.  Host-only.
+ */
+int nsf_plan_medium_info(nsf_plan plan, int* palette, long long* voxel_bytes);
 
 /*
  * Set a tuning option.  Options change speed: the tilings change results by
@@ -229,6 +247,75 @@ int nsf_set_medium_tensor(nsf_plan plan, const nsf_c128* eps, const nsf_c128* mu
                           const nsf_c128* xi, const nsf_c128* zeta, int on_device);
 
 /*
+ * Medium for the null space free eigenvalue problem (NFSEP, Thm 3.2; the
+ * else-branch of Algorithm 1): per voxel 3 x 3 complex eps_d, mu_d, xi_d,
+ * zeta_d laid out as for nsf_set_medium_tensor, host or device pointers.  No
+ * Hermitian, definiteness or reciprocity assumption (lossy, non-reciprocal
+ * and general bianisotropic media): only B = i [[zeta, mu], [-eps, -xi]] must
+ * be nonsingular at every voxel (Thm 3.1).  NSF_E_ARG for a non-finite entry
+ * or a pivot below 1e-13 of the voxel's largest entry, naming the voxel.  The
+ * library stores N = i J B^{-1} per voxel (J = [[0, I], [-I, 0]]; 36 complex
+ * values, 576 n bytes), which is A_r's middle factor when the medium does meet
+ * the Sec. 4.1 assumption.  The plan then serves nsf_apply_nfsep,
+ * nsf_nfsep_solve, nsf_eigs_nfsep, nsf_fields and nsf_apply_Ar (which applies
+ * diag(P_r^*, Q_r^*) N diag(P_r, Q_r)); nsf_cg_solve, nsf_eigs and the batch
+ * eigensolver return NSF_E_STATE.  Synchronises.
+ */
+int nsf_set_medium_nfsep(nsf_plan plan, const nsf_c128* eps, const nsf_c128* mu,
+                         const nsf_c128* xi, const nsf_c128* zeta, int on_device);
+
+/*
+ * out = K y with the NFSEP matrix of Thm 3.2,
+ *   K = diag(Sigma_r^{1/2} Q_r^*, Sigma_r^{1/2} P_r^*) B^{-1} diag(P_r Sigma_r^{1/2}, Q_r Sigma_r^{1/2}).
+ * y, out: device 4n vectors ([y_P; y_Q], frequency order; may alias).  Needs an
+ * NFSEP medium (NSF_E_STATE).  Asynchronous.
+ */
+int nsf_apply_nfsep(nsf_plan plan, const nsf_c128* y4n, nsf_c128* out4n);
+
+/*
+ * x = K^{-1} b, the zero-shift inverse that the shift-and-invert Arnoldi method
+ * of Sec. 4 applies, by restarted GMRES(restart) on the equivalent system
+ * Kern v = (i J4) Sigma'^{-1/2} b, x = Sigma'^{-1/2} v, where Kern =
+ * diag(P_r^*, Q_r^*) N diag(P_r, Q_r), (i J4)[a; b] = [i b; -i a] and Sigma' =
+ * diag(Sigma_r, Sigma_r) (K = Sigma'^{1/2} (i J4) Kern Sigma'^{1/2}).  GMRES
+ * starts from zero and stops when the recomputed residual of that system is
+ * <= rtol times its right-hand side (relres, host), or after maxit iterations
+ * (<= 0: 2000).  restart <= 0: 40.  b, x device, distinct.  Returns NSF_OK or
+ * NSF_NOT_CONVERGED; allocates and frees the GMRES basis ((restart + 1) 4n
+ * complex values).  Synchronises.
+ */
+int nsf_nfsep_solve(nsf_plan plan, const nsf_c128* b, nsf_c128* x, double rtol,
+                    int maxit, int restart, int* iters, double* relres);
+
+/*
+ * The nev eigenvalues of K (equivalently the nonzero ones of the GEP
+ * diag(C, C^*) x = omega B x, Thm 3.2) with positive real part and the smallest
+ * modulus, by shift-and-invert Arnoldi at zero shift (Sec. 4): Krylov-Schur
+ * restarted Arnoldi on Kern^{-1} B_r, B_r = i [[0, Sigma_r^{-1}], [-Sigma_r^{-1}, 0]],
+ * whose eigenvalues are 1/omega, with a GMRES solve of Kern per step
+ * (NSF_OPT_GMRES_RESTART) to relative residual inner_rtol.  For a medium that
+ * meets the assumption of Sec. 4.1 this is the invert Lanczos operator of
+ * nsf_eigs and the eigenvalues agree.  Basis of m = max_basis vectors (0:
+ * max(3 nev, nev + 8), at most 510), restart keeping nev + (m - nev)/2 Schur
+ * vectors, at most max_restarts restarts (0: 1000), start vector a seeded
+ * complex normal vector.  A pair is accepted with the exact residual
+ *   eta = ||K y - omega y|| / (|omega| ||y||) <= res_tol,
+ * omega = y^* K y / y^* y the Rayleigh quotient, y = Sigma'^{-1/2} x.
+ * Outputs: omega_host (nev complex, ascending modulus), Y_dev (nullable,
+ * device 4n x nev: the unit vectors x = Sigma'^{1/2} y, the scaled vectors
+ * Algorithm 1 hands to field recovery, so nsf_fields(x) gives E and H),
+ * resid_host (nullable, nev), stats (nullable; cg_* count GMRES iterations and
+ * solves, lanczos_steps Arnoldi steps, bytes_alg 896 n B per apply).
+ * Allocates and frees its bases ((m + 1) + (restart + 1) + 3 vectors of 4n
+ * complex values).  Returns NSF_OK, NSF_NOT_CONVERGED (results filled) or an
+ * error.  Synchronises.
+ */
+int nsf_eigs_nfsep(nsf_plan plan, int nev, double res_tol, double inner_rtol,
+                   int max_basis, int max_restarts, unsigned long long seed,
+                   nsf_c128* omega_host, nsf_c128* Y_dev, double* resid_host,
+                   nsf_stats* stats);
+
+/*
  * Basis applies (Thm 2.5; T by twisted FFT, Sec. 4.2).  All pointers device.
  *   nsf_apply_Pr : y (2n, [y_a; y_b]) -> x (3n) = P_r y
  *   nsf_apply_Qr : y (2n, [y_c; y_d]) -> x (3n) = Q_r y
@@ -302,7 +389,8 @@ int nsf_eigs(nsf_plan plan, int nev, double res_tol, double cg_rtol,
 /*
  * Electric and magnetic fields of a pencil eigenvector (Algorithm 1, last
  * step): [E; H] = B^{-1} diag(P_r, Q_r) y, B the medium matrix of the GEP
- * (Sec. 3).  y: device 4n vector (as returned by nsf_eigs); eh: device 6n,
+ * (Sec. 3).  y: device 4n vector (as returned by nsf_eigs, or the scaled
+ * vector x of nsf_eigs_nfsep for an NFSEP medium); eh: device 6n,
  * [E_x; E_y; E_z; H_x; H_y; H_z], n each, voxel order g, carrying the Bloch
  * phase of k.  The pair (omega, [E; H]) then solves
  * diag(C, C^*) [E; H] = omega B [E; H].  Needs a medium (NSF_E_STATE).
@@ -385,6 +473,15 @@ int nsf_batch_autotune(nsf_batch batch, int reps, int* shapes_tuned);
  * eigenvector of w[j] (nullable).  1 <= m <= 512.
  */
 int nsf_hermitian_eig(int m, const nsf_c128* H, double* w, nsf_c128* V);
+
+/*
+ * Dense complex Schur form on the host, A = Z T Z^* (Hessenberg reduction and
+ * shifted QR, then adjacent swaps), with the diagonal of T in the order the
+ * NFSEP eigensolver wants its Ritz values: positive real part first, then
+ * descending modulus.  The small projected problem of nsf_eigs_nfsep.
+ * A, T, Z: host m x m, column-major; A only read.  1 <= m <= 512.
+ */
+int nsf_schur_sorted(int m, const nsf_c128* A, nsf_c128* T, nsf_c128* Z);
 
 /* Facts about a HIP device (host call; touches the device runtime). */
 typedef struct {

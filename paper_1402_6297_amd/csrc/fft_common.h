@@ -309,11 +309,35 @@ __device__ __forceinline__ void general_apply(const double2* __restrict__ Mu, do
   }
 }
 
+// NFSEP media: [E; H] <- N [E; H] / n with N = i J B^{-1} the voxel's full 6 x 6
+// factor, J = [[0, I], [-I, 0]] (Thm 3.2; N is the Hermitian middle factor of
+// A_r when the medium meets the assumption of Sec. 4.1), row-major.
+__device__ __forceinline__ void full_apply(const double2* __restrict__ N, double inv_n, double2* E,
+                                           double2* H) {
+  const double2 v[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
+  double2 o[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double2 acc = make_double2(0, 0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc = cadd(acc, cmul(N[6 * i + j], v[j]));
+    o[i] = cscale(acc, inv_n);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    E[c] = o[c];
+    H[c] = o[3 + c];
+  }
+}
+
 // The constitutive step of voxel gi for any medium kind.
 __device__ __forceinline__ void medium_apply_at(const MediumView& m, long long gi, double inv_n, double2* E,
                                                 double2* H) {
+  const long long slot = m.pidx ? (long long)m.pidx[gi] : gi;
   if (m.kind == kMedGeneral)
-    general_apply(m.mg + gi * kGenEntries, inv_n, E, H);
+    general_apply(m.mg + slot * kGenEntries, inv_n, E, H);
+  else if (m.kind == kMedNfsep)
+    full_apply(m.mf + slot * kFullEntries, inv_n, E, H);
   else
     medium_apply(m, m.eg[gi], inv_n, E, H);
 }

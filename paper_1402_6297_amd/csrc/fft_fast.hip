@@ -760,7 +760,7 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
   if (np_mid) *np_mid = 0;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
-  if (g.mid_pairs && med.kind != kMedGeneral) {  // general media couple all six fields
+  if (g.mid_pairs && !six_coupled(med.kind)) {  // general media couple all six fields
     const size_t lmax = lds_limit() - 1024;  // room for the kernel's static LDS (reductions)
     int P = pick_cols(g.n1, P_want);
     while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax)) P /= 2;

@@ -625,6 +625,8 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
 int make_run(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis, int max_restarts,
              unsigned long long seed, Run& r) {
   if (p->medium_kind == kMedNone) return set_error(p, NSF_E_STATE, "no medium set");
+  if (p->medium_kind == kMedNfsep)
+    return set_error(p, NSF_E_STATE, "an NFSEP medium has no HHPD pencil; use nsf_eigs_nfsep");
   const long long n = p->geom.n, len = 4 * n;
   if (nev < 1 || nev > 256 || 2LL * nev >= len) return set_error(p, NSF_E_ARG, "nev out of range");
   if (!(res_tol > 0.0) || !(cg_rtol > 0.0)) return set_error(p, NSF_E_ARG, "tolerances must be > 0");

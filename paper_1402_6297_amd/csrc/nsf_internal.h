@@ -59,17 +59,33 @@ struct Geom {
   int mid_pairs = 1; // fused z pass: 1 one field pair per workgroup, 0 all six fields
 };
 
-enum MediumKind { kMedNone = 0, kMedChiral = 1, kMedPseudo = 2, kMedGeneral = 3 };
+enum MediumKind { kMedNone = 0, kMedChiral = 1, kMedPseudo = 2, kMedGeneral = 3, kMedNfsep = 4 };
 
 // Entries of the general per-voxel middle factor kept per voxel: the upper
 // triangle of a 6 x 6 Hermitian matrix, row by row.
 constexpr int kGenEntries = 21;
+// Entries of the NFSEP per-voxel factor i J B^{-1}: a full 6 x 6 matrix, row-major.
+constexpr int kFullEntries = 36;
+
+// Algorithmic HBM bytes per voxel of one apply with the NFSEP factor: read the
+// 4n input (64), write and read six fields (96 + 96), read 36 complex entries
+// (576), write the 4n output (64).
+constexpr int kNfsepApplyBytesPerVoxel = 896;
+
+// Largest palette of distinct per-voxel factors (general and NFSEP media); a
+// medium with more distinct voxels keeps its factors per voxel.
+constexpr int kPaletteMax = 4096;
+
+// Media whose per-voxel factor couples all six field components (no pair passes).
+inline bool six_coupled(int kind) { return kind == kMedGeneral || kind == kMedNfsep; }
 
 struct MediumView {
   int kind;
   int pa, pb, po;        // pseudochiral coupled axes and the third axis
   const double2* eg;     // per voxel (eps, gamma)
-  const double2* mg;     // general media: kGenEntries per voxel
+  const double2* mg;     // general media: kGenEntries per voxel (or per palette entry)
+  const double2* mf;     // NFSEP media: kFullEntries per voxel (or per palette entry)
+  const unsigned short* pidx;  // palette index per voxel, or null (factors stored per voxel)
 };
 
 // Which half of the synthesis / projection a pass performs.
@@ -290,6 +306,9 @@ struct nsf_plan_s {
   int pa = 0, pb = 1, po = 2;
   double2* d_medium = nullptr;  // (eps, gamma) per voxel
   double2* d_mgen = nullptr;    // general media: 6x6 middle factor per voxel (upper triangle)
+  double2* d_mfull = nullptr;   // NFSEP media: 6x6 factor i J B^{-1} per voxel (row-major)
+  unsigned short* d_pidx = nullptr;  // palette index per voxel (general / NFSEP media)
+  int palette = 0;              // distinct voxel factors in the palette, 0: stored per voxel
 
   // workspace
   double2* d_fields = nullptr;  // 6 n
@@ -325,6 +344,8 @@ struct nsf_plan_s {
   int opt_cg_start = 1;     // eigensolver CG starts from the Galerkin solution in span(V)
   int opt_verify = 0;       // multiplicity checks after convergence (nsf_eigs)
   int opt_ortho_gate = 1;   // skip negligible Gram-Schmidt updates on the device
+  int opt_gmres_restart = 40;  // GMRES restart length of the NFSEP eigensolver
+  int opt_palette = 1;      // general / NFSEP media: palette of distinct voxel factors
 
   std::string last_error;
 };

@@ -1,11 +1,11 @@
 // Plan construction, medium upload and the basis / A_r / B_r applies (host).
 #include <chrono>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
-
-#include <complex>
 #include <string>
+#include <unordered_map>
 
 #include "nsf_internal.h"
 
@@ -93,6 +93,8 @@ MediumView medium_view(nsf_plan p) {
   m.po = p->po;
   m.eg = p->d_medium;
   m.mg = p->d_mgen;
+  m.mf = p->d_mfull;
+  m.pidx = p->palette > 0 ? p->d_pidx : nullptr;
   return m;
 }
 
@@ -116,7 +118,7 @@ hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post
 hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid, int* np_mid) {
   const Geom& g = p->geom;
   if (np_mid) *np_mid = 0;
-  if (p->opt_fft_path == 2 && wave_mid_ok(g) && p->medium_kind != kMedGeneral)
+  if (p->opt_fft_path == 2 && wave_mid_ok(g) && !six_coupled(p->medium_kind))
     return launch_wave_z_mid(g, p->tabs, medium_view(p), fld, skip, p->stream);
   if (p->opt_fft_path != 1 && fast_axis(g.n3))
     return launch_fast_z_mid(g, p->tabs, medium_view(p), fld, p->opt_mid_cols, skip, p->stream, nullptr, 1,
@@ -301,6 +303,8 @@ void nsf_plan_destroy(nsf_plan p) {
     hipHostFree(p->h_res);
     if (p->d_medium) hipFree(p->d_medium);
     if (p->d_mgen) hipFree(p->d_mgen);
+    if (p->d_mfull) hipFree(p->d_mfull);
+    if (p->d_pidx) hipFree(p->d_pidx);
     if (p->d_cg && !p->ws) hipFree(p->d_cg);
     if (p->d_basis && !p->ws) hipFree(p->d_basis);
     if (p->d_small && !p->ws) hipFree(p->d_small);
@@ -379,6 +383,14 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
       if (value < 0 || value > 16) return set_error(p, NSF_E_ARG, "NSF_OPT_VERIFY takes 0..16");
       p->opt_verify = value;
       return NSF_OK;
+    case NSF_OPT_MEDIUM_PALETTE:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_MEDIUM_PALETTE takes 0 or 1");
+      p->opt_palette = value;
+      return NSF_OK;
+    case NSF_OPT_GMRES_RESTART:
+      if (value < 4 || value > 500) return set_error(p, NSF_E_ARG, "NSF_OPT_GMRES_RESTART takes 4..500");
+      p->opt_gmres_restart = value;
+      return NSF_OK;
     case NSF_OPT_ORTHO_GATE:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_ORTHO_GATE takes 0 or 1");
       p->opt_ortho_gate = value;
@@ -390,6 +402,20 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
     default:
       return set_error(p, NSF_E_ARG, "unknown option");
   }
+}
+
+int nsf_plan_medium_info(nsf_plan p, int* palette, long long* voxel_bytes) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  const int k = p->medium_kind;
+  const int entries = k == kMedGeneral ? kGenEntries : k == kMedNfsep ? kFullEntries : 0;
+  if (palette) *palette = entries ? p->palette : 0;
+  if (voxel_bytes) {
+    if (k == kMedNone) *voxel_bytes = 0;
+    else if (!entries) *voxel_bytes = (long long)sizeof(double2);  // (eps, gamma) per voxel
+    else if (p->palette > 0) *voxel_bytes = (long long)sizeof(unsigned short);
+    else *voxel_bytes = (long long)sizeof(double2) * entries;
+  }
+  return NSF_OK;
 }
 
 int nsf_plan_query(nsf_plan p, long long* n, int* medium_kind, double* sigma_min, double* sigma_max) {
@@ -530,9 +556,150 @@ bool hpd_inverse3(const M3& x, M3& inv) {
   return true;
 }
 
+// Upload per-voxel factors (E complex values per voxel) to *dst: as a palette of
+// the distinct voxel factors plus a 16-bit index per voxel when there are at
+// most kPaletteMax of them (bitwise equality), else per voxel.  *dst has room
+// for n E values once allocated.
+int upload_factors(nsf_plan p, const std::vector<double2>& M, int E, double2** dst) {
+  const long long n = p->geom.n;
+  std::vector<double2> pal;
+  std::vector<unsigned short> idx((size_t)n);
+  std::unordered_map<unsigned long long, std::vector<int>> seen;
+  bool fits = p->opt_palette != 0;
+  for (long long g = 0; g < n && fits; ++g) {
+    const double2* v = M.data() + (size_t)g * E;
+    unsigned long long h = 1469598103934665603ULL;  // FNV-1a over the bytes
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(v);
+    for (size_t i = 0; i < sizeof(double2) * E; ++i) h = (h ^ b[i]) * 1099511628211ULL;
+    int found = -1;
+    auto& cand = seen[h];
+    for (int c : cand)
+      if (!std::memcmp(pal.data() + (size_t)c * E, v, sizeof(double2) * E)) {
+        found = c;
+        break;
+      }
+    if (found < 0) {
+      found = (int)(pal.size() / E);
+      if (found >= kPaletteMax) {
+        fits = false;
+        break;
+      }
+      pal.insert(pal.end(), v, v + E);
+      cand.push_back(found);
+    }
+    idx[(size_t)g] = (unsigned short)found;
+  }
+  if (!*dst) NSF_HIP(p, hipMalloc(dst, sizeof(double2) * (size_t)n * E));
+  if (fits) {
+    if (!p->d_pidx) NSF_HIP(p, hipMalloc(&p->d_pidx, sizeof(unsigned short) * (size_t)n));
+    NSF_HIP(p, hipMemcpyAsync(*dst, pal.data(), sizeof(double2) * pal.size(), hipMemcpyHostToDevice, p->stream));
+    NSF_HIP(p, hipMemcpyAsync(p->d_pidx, idx.data(), sizeof(unsigned short) * idx.size(), hipMemcpyHostToDevice,
+                              p->stream));
+    p->palette = (int)(pal.size() / E);
+  } else {
+    NSF_HIP(p, hipMemcpyAsync(*dst, M.data(), sizeof(double2) * M.size(), hipMemcpyHostToDevice, p->stream));
+    p->palette = 0;
+  }
+  NSF_HIP(p, hipStreamSynchronize(p->stream));
+  return NSF_OK;
+}
+
+// Inverse of a complex 6 x 6 matrix by Gauss-Jordan elimination with partial
+// pivoting.  False when a pivot falls to tiny * max |entry| (numerically singular).
+bool inverse6(cplx a[6][6], cplx inv[6][6], double tiny) {
+  double amax = 0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      amax = std::max(amax, std::abs(a[i][j]));
+      inv[i][j] = i == j ? 1.0 : 0.0;
+    }
+  if (!(amax > 0)) return false;
+  for (int c = 0; c < 6; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 6; ++r)
+      if (std::abs(a[r][c]) > std::abs(a[piv][c])) piv = r;
+    if (!(std::abs(a[piv][c]) > tiny * amax)) return false;
+    if (piv != c)
+      for (int j = 0; j < 6; ++j) {
+        std::swap(a[c][j], a[piv][j]);
+        std::swap(inv[c][j], inv[piv][j]);
+      }
+    const cplx d = 1.0 / a[c][c];
+    for (int j = 0; j < 6; ++j) {
+      a[c][j] *= d;
+      inv[c][j] *= d;
+    }
+    for (int r = 0; r < 6; ++r) {
+      if (r == c) continue;
+      const cplx f = a[r][c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < 6; ++j) {
+        a[r][j] -= f * a[c][j];
+        inv[r][j] -= f * inv[c][j];
+      }
+    }
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
+
+int nsf_set_medium_nfsep(nsf_plan p, const nsf_c128* eps, const nsf_c128* mu, const nsf_c128* xi,
+                         const nsf_c128* zeta, int on_device) {
+  if (!p) return set_error(nullptr, NSF_E_ARG, "plan is NULL");
+  if (!eps || !mu || !xi || !zeta) return set_error(p, NSF_E_ARG, "a tensor field is NULL");
+  const long long n = p->geom.n;
+  const size_t cnt = 9 * (size_t)n;
+  std::vector<double2> h[4];
+  const double2* src[4] = {reinterpret_cast<const double2*>(eps), reinterpret_cast<const double2*>(mu),
+                           reinterpret_cast<const double2*>(xi), reinterpret_cast<const double2*>(zeta)};
+  if (on_device) {
+    const int rc = ensure_device(p);
+    if (rc) return rc;
+    for (int f = 0; f < 4; ++f) {
+      h[f].resize(cnt);
+      NSF_HIP(p, hipMemcpyAsync(h[f].data(), src[f], sizeof(double2) * cnt, hipMemcpyDeviceToHost, p->stream));
+      src[f] = h[f].data();
+    }
+    NSF_HIP(p, hipStreamSynchronize(p->stream));
+  }
+  const cplx I(0.0, 1.0);
+  std::vector<double2> N((size_t)n * kFullEntries);
+  for (long long g = 0; g < n; ++g) {
+    const M3 E = load3(src[0] + 9 * g), U = load3(src[1] + 9 * g), X = load3(src[2] + 9 * g),
+             Z = load3(src[3] + 9 * g);
+    for (const M3* t : {&E, &U, &X, &Z})
+      for (auto& row : t->a)
+        for (auto& v : row)
+          if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+            return set_error(p, NSF_E_ARG, "medium has a non-finite value at voxel " + std::to_string(g));
+    // B = i [[zeta, mu], [-eps, -xi]] (Sec. 3)
+    cplx B[6][6], Bi[6][6];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        B[i][j] = I * Z.a[i][j];
+        B[i][3 + j] = I * U.a[i][j];
+        B[3 + i][j] = -I * E.a[i][j];
+        B[3 + i][3 + j] = -I * X.a[i][j];
+      }
+    if (!inverse6(B, Bi, 1e-13))
+      return set_error(p, NSF_E_ARG, "B = i[[zeta, mu], [-eps, -xi]] is singular at voxel " + std::to_string(g));
+    // N = i J B^{-1}: rows 0..2 = i (B^{-1}) rows 3..5, rows 3..5 = -i (B^{-1}) rows 0..2
+    double2* out = N.data() + (size_t)g * kFullEntries;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        const cplx v = i < 3 ? I * Bi[3 + i][j] : -I * Bi[i - 3][j];
+        out[6 * i + j] = make_double2(v.real(), v.imag());
+      }
+  }
+  int rc = ensure_device(p);
+  if (rc) return rc;
+  if ((rc = upload_factors(p, N, kFullEntries, &p->d_mfull))) return rc;
+  p->medium_kind = kMedNfsep;
+  return NSF_OK;
+}
 
 int nsf_set_medium_tensor(nsf_plan p, const nsf_c128* eps, const nsf_c128* mu, const nsf_c128* xi,
                           const nsf_c128* zeta, int on_device) {
@@ -598,11 +765,9 @@ int nsf_set_medium_tensor(nsf_plan p, const nsf_c128* eps, const nsf_c128* mu, c
         out[k] = make_double2(v.real(), v.imag());
       }
   }
-  const int rc = ensure_device(p);
+  int rc = ensure_device(p);
   if (rc) return rc;
-  if (!p->d_mgen) NSF_HIP(p, hipMalloc(&p->d_mgen, sizeof(double2) * M.size()));
-  NSF_HIP(p, hipMemcpyAsync(p->d_mgen, M.data(), sizeof(double2) * M.size(), hipMemcpyHostToDevice, p->stream));
-  NSF_HIP(p, hipStreamSynchronize(p->stream));
+  if ((rc = upload_factors(p, M, kGenEntries, &p->d_mgen))) return rc;
   p->medium_kind = kMedGeneral;
   return NSF_OK;
 }

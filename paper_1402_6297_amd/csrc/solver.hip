@@ -298,6 +298,8 @@ int nsf_cg_solve(nsf_plan p, const nsf_c128* b, nsf_c128* x, double rtol, int ma
   if ((const void*)b == (const void*)x) return set_error(p, NSF_E_ARG, "b and x must be distinct");
   if (!(rtol >= 0.0)) return set_error(p, NSF_E_ARG, "rtol must be >= 0");
   if (p->medium_kind == kMedNone) return set_error(p, NSF_E_STATE, "no medium set");
+  if (p->medium_kind == kMedNfsep)
+    return set_error(p, NSF_E_STATE, "an NFSEP medium has no positive definite A_r; use nsf_nfsep_solve");
   long long mv = 0;
   return cg_solve_dev(p, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxit,
                       iters, relres, &mv);

@@ -30,6 +30,7 @@ NSF_E_HIP = -7
 NSF_E_STATE = -8
 
 NSF_MEDIUM_NONE, NSF_MEDIUM_CHIRAL, NSF_MEDIUM_PSEUDOCHIRAL, NSF_MEDIUM_GENERAL = 0, 1, 2, 3
+NSF_MEDIUM_NFSEP = 4
 
 NSF_OPT_FFT_PATH = 1
 NSF_OPT_MID_COLS = 2
@@ -40,6 +41,8 @@ NSF_OPT_MID_PAIRS = 6
 NSF_OPT_CG_START = 7
 NSF_OPT_VERIFY = 8
 NSF_OPT_ORTHO_GATE = 9
+NSF_OPT_GMRES_RESTART = 10
+NSF_OPT_MEDIUM_PALETTE = 11
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",
@@ -49,7 +52,8 @@ EXPORTED = [
     "nsf_hermitian_eig", "nsf_device_info", "nsf_status_string", "nsf_last_error",
     "nsf_batch_create", "nsf_batch_plan", "nsf_batch_eigs", "nsf_batch_destroy",
     "nsf_plan_autotune", "nsf_batch_autotune", "nsf_plan_workspace_size", "nsf_plan_set_workspace",
-    "nsf_fields", "nsf_eigs_set_start",
+    "nsf_fields", "nsf_eigs_set_start", "nsf_schur_sorted", "nsf_set_medium_nfsep", "nsf_apply_nfsep",
+    "nsf_nfsep_solve", "nsf_eigs_nfsep", "nsf_plan_medium_info",
 ]
 
 
@@ -123,6 +127,12 @@ def lib():
         "nsf_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, VP, DP, C.POINTER(nsf_stats)]),
         "nsf_eig_grad": (I, [P, I, DP, VP, DP, VP, VP]),
         "nsf_hermitian_eig": (I, [I, VP, DP, VP]),
+        "nsf_schur_sorted": (I, [I, VP, VP, VP]),
+        "nsf_plan_medium_info": (I, [P, C.POINTER(I), C.POINTER(C.c_longlong)]),
+        "nsf_set_medium_nfsep": (I, [P, VP, VP, VP, VP, I]),
+        "nsf_apply_nfsep": (I, [P, VP, VP]),
+        "nsf_nfsep_solve": (I, [P, VP, VP, D, I, I, C.POINTER(I), DP]),
+        "nsf_eigs_nfsep": (I, [P, I, D, D, I, I, C.c_ulonglong, VP, VP, DP, C.POINTER(nsf_stats)]),
         "nsf_device_info": (I, [I, C.POINTER(nsf_device)]),
         "nsf_batch_create": (I, [C.POINTER(P), I, VP, VP, D, D, D, VP]),
         "nsf_batch_plan": (I, [P, I, C.POINTER(P)]),
@@ -225,19 +235,28 @@ def nsf_set_medium_pseudochiral(plan, axis_a, axis_b, eps, gamma):
     return _check(lib().nsf_set_medium_pseudochiral(plan, int(axis_a), int(axis_b), pe, pg, on_dev), plan)
 
 
-def nsf_set_medium_tensor(plan, eps, mu, xi, zeta):
-    """General medium: four (n, 3, 3) complex128 tensor fields (numpy on the host, or
-    contiguous torch tensors on the device), voxel order g = i1 + n1 i2 + n1 n2 i3."""
+def _set_tensors(name, plan, eps, mu, xi, zeta):
     fields = [eps, mu, xi, zeta]
     try:
         import torch
         if isinstance(eps, torch.Tensor):
             ptrs = [_dptr(t, "c128") for t in fields]
-            return _check(lib().nsf_set_medium_tensor(plan, *ptrs, 1), plan)
+            return _check(getattr(lib(), name)(plan, *ptrs, 1), plan)
     except ImportError:  # pragma: no cover
         pass
     keep = [np.ascontiguousarray(np.reshape(f, (-1, 3, 3)), dtype=np.complex128) for f in fields]
-    return _check(lib().nsf_set_medium_tensor(plan, *[C.c_void_p(k.ctypes.data) for k in keep], 0), plan)
+    return _check(getattr(lib(), name)(plan, *[C.c_void_p(k.ctypes.data) for k in keep], 0), plan)
+
+
+def nsf_set_medium_tensor(plan, eps, mu, xi, zeta):
+    """General medium: four (n, 3, 3) complex128 tensor fields (numpy on the host, or
+    contiguous torch tensors on the device), voxel order g = i1 + n1 i2 + n1 n2 i3."""
+    return _set_tensors("nsf_set_medium_tensor", plan, eps, mu, xi, zeta)
+
+
+def nsf_set_medium_nfsep(plan, eps, mu, xi, zeta):
+    """NFSEP medium (any nonsingular B): tensors laid out as for nsf_set_medium_tensor."""
+    return _set_tensors("nsf_set_medium_nfsep", plan, eps, mu, xi, zeta)
 
 
 def _apply(name, plan, src, dst):
@@ -289,6 +308,35 @@ def nsf_cg_solve(plan, b, x, rtol=1e-10, maxit=10000):
     return st, it.value, rel.value
 
 
+def nsf_plan_medium_info(plan):
+    pal, vb = C.c_int(), C.c_longlong()
+    _check(lib().nsf_plan_medium_info(plan, C.byref(pal), C.byref(vb)), plan)
+    return {"palette": pal.value, "voxel_bytes": vb.value}
+
+
+def nsf_apply_nfsep(plan, y4n, out4n):
+    return _apply("nsf_apply_nfsep", plan, y4n, out4n)
+
+
+def nsf_nfsep_solve(plan, b, x, rtol=1e-10, maxit=0, restart=0):
+    it, rel = C.c_int(), C.c_double()
+    st = _check(lib().nsf_nfsep_solve(plan, _dptr(b, "c128"), _dptr(x, "c128"), float(rtol), int(maxit),
+                                      int(restart), C.byref(it), C.byref(rel)), plan)
+    return st, it.value, rel.value
+
+
+def nsf_eigs_nfsep(plan, nev, res_tol=1e-8, inner_rtol=1e-10, max_basis=0, max_restarts=0, seed=0, Y=None):
+    """Returns (status, omega[nev] complex, resid[nev], stats dict); Y (4n x nev device) filled if given."""
+    omega = np.zeros(nev, dtype=np.complex128)
+    resid = np.zeros(nev)
+    st = nsf_stats()
+    yp = _dptr(Y, "c128") if Y is not None else None
+    status = _check(lib().nsf_eigs_nfsep(plan, int(nev), float(res_tol), float(inner_rtol), int(max_basis),
+                                         int(max_restarts), C.c_ulonglong(seed), C.c_void_p(omega.ctypes.data),
+                                         yp, resid.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)), plan)
+    return status, omega, resid, st.as_dict()
+
+
 def nsf_eigs(plan, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, max_restarts=0, seed=0, Y=None):
     """Returns (status, omega[nev], resid[nev], stats dict); Y (4n x nev device) is filled if given."""
     omega = np.zeros(nev)
@@ -318,6 +366,17 @@ def nsf_hermitian_eig(H):
     _check(lib().nsf_hermitian_eig(m, C.c_void_p(H.ctypes.data), w.ctypes.data_as(C.POINTER(C.c_double)),
                                    C.c_void_p(V.ctypes.data)))
     return w, V
+
+
+def nsf_schur_sorted(A):
+    """Complex Schur form A = Z T Z^* with the NFSEP Ritz order (host)."""
+    A = np.asfortranarray(A, dtype=np.complex128)
+    m = A.shape[0]
+    T = np.zeros((m, m), dtype=np.complex128, order="F")
+    Z = np.zeros((m, m), dtype=np.complex128, order="F")
+    _check(lib().nsf_schur_sorted(m, C.c_void_p(A.ctypes.data), C.c_void_p(T.ctypes.data),
+                                  C.c_void_p(Z.ctypes.data)))
+    return T, Z
 
 
 def nsf_device_info(device=0):
@@ -502,6 +561,21 @@ class Plan:
 
     def set_tensor(self, eps, mu, xi, zeta):
         return nsf_set_medium_tensor(self.handle, eps, mu, xi, zeta)
+
+    def medium_info(self):
+        return nsf_plan_medium_info(self.handle)
+
+    def set_nfsep(self, eps, mu, xi, zeta):
+        return nsf_set_medium_nfsep(self.handle, eps, mu, xi, zeta)
+
+    def K(self, y, out):
+        return nsf_apply_nfsep(self.handle, y, out)
+
+    def nfsep_solve(self, b, x, **kw):
+        return nsf_nfsep_solve(self.handle, b, x, **kw)
+
+    def eigs_nfsep(self, nev, **kw):
+        return nsf_eigs_nfsep(self.handle, nev, **kw)
 
     def Ar(self, u, out):
         return nsf_apply_Ar(self.handle, u, out)

@@ -108,6 +108,8 @@ def test_status_strings():
     (nsf.NSF_OPT_CG_START, [0, 1], [-1, 2]),
     (nsf.NSF_OPT_VERIFY, [0, 1, 16], [-1, 17]),
     (nsf.NSF_OPT_ORTHO_GATE, [0, 1], [-1, 2]),
+    (nsf.NSF_OPT_GMRES_RESTART, [4, 40, 500], [3, 501]),
+    (nsf.NSF_OPT_MEDIUM_PALETTE, [0, 1], [-1, 2]),
 ])
 def test_plan_options_validate(option, good, bad):
     p = nsf.nsf_plan_create(8, 8, 8, 1.0, (0.1, 0.2, 0.3), stream=0)
@@ -182,5 +184,79 @@ def test_workspace_size_and_validation():
         assert nsf.lib().nsf_plan_set_workspace(p, ctypes.c_void_p(0x100000), 1024) == nsf.NSF_E_ARG
         with pytest.raises(nsf.NsfError):
             nsf.nsf_plan_workspace_size(p, 0)
+    finally:
+        nsf.nsf_plan_destroy(p)
+
+
+def _key_order_ok(d):
+    """Positive real part first, then descending modulus."""
+    for a, b in zip(d[:-1], d[1:]):
+        pa, pb = a.real > 0, b.real > 0
+        if pa != pb:
+            if not pa:
+                return False
+        elif abs(a) < abs(b) * (1 - 1e-12):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("m,kind", [(1, "random"), (2, "random"), (9, "random"), (30, "random"),
+                                    (24, "hermitian"), (16, "normal_pairs"), (40, "hessenberg_plus_row")])
+def test_schur_sorted_matches_lapack(m, kind):
+    """The host Schur form of the NFSEP eigensolver: A = Z T Z^*, Z unitary, T
+    upper triangular with LAPACK's eigenvalues on its diagonal, in the wanted
+    order; the shapes include the restarted Krylov-Schur matrix (triangular
+    block plus one full row) and a spectrum of +- pairs."""
+    rng = np.random.default_rng(m)
+    X = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    if kind == "hermitian":
+        A = X + X.conj().T
+    elif kind == "normal_pairs":
+        w = rng.standard_normal(m // 2) + 0.1j * rng.standard_normal(m // 2)
+        Q, _ = np.linalg.qr(X)
+        A = Q @ np.diag(np.concatenate([w, -w])) @ Q.conj().T
+    elif kind == "hessenberg_plus_row":
+        A = np.triu(X, -1)
+        k = m // 2
+        A[:k, :k] = np.triu(A[:k, :k])
+        A[k, :k] = rng.standard_normal(k)
+    else:
+        A = X
+    T, Z = nsf.nsf_schur_sorted(A)
+    scale = np.abs(A).max()
+    assert np.abs(np.tril(T, -1)).max(initial=0.0) == 0.0
+    assert np.abs(Z.conj().T @ Z - np.eye(m)).max() < 1e-12
+    assert np.abs(Z @ T @ Z.conj().T - A).max() < 1e-12 * m * scale
+    d = np.diag(T)
+    ref = list(np.linalg.eigvals(A))
+    for x in d:
+        j = int(np.argmin([abs(x - y) for y in ref]))
+        assert abs(x - ref[j]) < 1e-9 * scale
+        ref.pop(j)
+    assert _key_order_ok(d)
+
+
+@pytest.mark.parametrize("breaker,msg", [("singular", "is singular at voxel"),
+                                         ("nonfinite", "non-finite value at voxel")])
+def test_nfsep_medium_validation(breaker, msg):
+    from paper_1402_6297_amd import media
+
+    eps, mu, xi, zeta = media.random_nonhhpd(4, seed=2)
+    g = 21
+    if breaker == "singular":  # B = i [[0, 0], [-eps, 0]]
+        mu[g] = 0.0
+        xi[g] = 0.0
+        zeta[g] = 0.0
+    else:
+        xi[g, 1, 2] = np.nan
+    p = nsf.nsf_plan_create(4, 4, 4, 1.0, (0.1, 0.2, 0.3), stream=0)
+    try:
+        with pytest.raises(nsf.NsfError) as e:
+            nsf.nsf_set_medium_nfsep(p, eps, mu, xi, zeta)
+        assert e.value.status == nsf.NSF_E_ARG
+        assert msg in str(e.value) and f"voxel {g}" in str(e.value)
+        with pytest.raises(nsf.NsfError) as e:
+            nsf.nsf_eigs_nfsep(p, 4)
+        assert e.value.status == nsf.NSF_E_STATE
     finally:
         nsf.nsf_plan_destroy(p)

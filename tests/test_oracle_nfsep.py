@@ -128,3 +128,12 @@ def test_residual_and_rayleigh_of_dense_eigenvector():
     assert abs(nfsep.rayleigh(z, grid, K0, t) - w[j]) < 1e-12 * abs(w[j])
     d = 1e-6 * abs(w[j])
     assert abs(nfsep.residual(z, w[j] + d, grid, K0, t) - 1e-6) < 1e-9
+
+
+@pytest.mark.parametrize("grid", [(4, 4, 4), (6, 6, 6)])
+def test_sparse_gep_shift_invert_matches_dense(grid):
+    """The FFT-free route on the 6n GEP (the independent reference at 16^3)."""
+    t = _tens(media.lossy_sphere_tensors(*grid, radius=0.4))
+    ref = nfsep.smallest_positive(nfsep.eigs_dense(grid, K0, t), 5)
+    w = nfsep.gep_shift_invert(grid, K0, t, nev=5)
+    assert np.abs(w - ref).max() <= 1e-10 * np.abs(ref).max()
