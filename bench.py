@@ -418,15 +418,19 @@ def cpu_baseline(w, eps, gam, budget_s=20.0):
                 host_cpu=platform.processor() or platform.machine())
 
 
+# Sources the A_r apply kernels are compiled from (the passes and their shared
+# device code); stored traffic figures apply only while these are unchanged.
+APPLY_SOURCES = ("fft_fast.hip", "fft_passes.hip", "fft_wave.hip", "fft_common.h", "nsf_internal.h")
+
+
 def kernel_source_hash():
-    """Hash of the HIP sources: stored traffic figures apply only to these kernels."""
+    """Hash of the A_r apply kernel sources."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_1402_6297_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in APPLY_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

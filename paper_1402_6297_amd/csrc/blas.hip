@@ -283,6 +283,68 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, in
   }
 }
 
+// q-free schedule, after the fused z pass: st->pap = sum of its partials.
+__global__ __launch_bounds__(kRedThreads) void k_cgf_alpha(const double* part_mid, int np_mid, CgState* st,
+                                                           const InstDesc* insts) {
+  if (insts) {
+    part_mid = insts[blockIdx.x].cg.part_mid;
+    st = insts[blockIdx.x].cg.st;
+  }
+  if (st->done) return;
+  double2 a = make_double2(fold_doubles(part_mid, np_mid, 1), 0);
+  a = block_sum(a);
+  if (threadIdx.x == 0) st->pap = a.x;
+}
+
+// q-free schedule, after the last pass (which set r = r - alpha q): the new
+// |r|^2, alpha and beta of this iteration, and the convergence test.
+__global__ __launch_bounds__(kRedThreads) void k_cgf_step_qf(const double* part, int nparts, CgState* st,
+                                                             const InstDesc* insts) {
+  if (insts) {
+    part = insts[blockIdx.x].cg.part_out;
+    st = insts[blockIdx.x].cg.st;
+  }
+  if (st->done) return;
+  double2 v = make_double2(fold_doubles(part, nparts, 1), 0);
+  v = block_sum(v);
+  if (threadIdx.x == 0) {
+    const double pap = st->pap, rr = st->rr, rn = v.x;
+    if (!(pap > 0.0) || !isfinite(pap)) {  // the last pass left r unchanged
+      st->status = NSF_E_BREAKDOWN;
+      st->done = 1;
+      return;
+    }
+    st->alpha = rr / pap;
+    st->beta = rn / rr;
+    st->rr = rn;
+    st->iter += 1;
+    if (!isfinite(rn)) {
+      st->status = NSF_E_BREAKDOWN;
+      st->done = 1;
+    } else if (rn <= st->thresh) {
+      st->status = NSF_OK;
+      st->done = 1;
+    } else if (st->iter >= st->maxit) {
+      st->status = NSF_NOT_CONVERGED;
+      st->done = 1;
+    }
+  }
+}
+
+// x = x + alpha p: the update the q-free schedule leaves for the next first
+// pass, applied once when the solve has ended (not after a breakdown).
+__global__ void k_cg_finish(double2* __restrict__ x, const double2* __restrict__ p, long long len,
+                            const CgState* st) {
+  if (st->status == NSF_E_BREAKDOWN || st->iter == 0) return;
+  const double al = st->alpha;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double2 pv = p[i];
+    const double2 xv = x[i];
+    x[i] = make_double2(xv.x + al * pv.x, xv.y + al * pv.y);
+  }
+}
+
 // ------------------------------------------------------- multi-vector ops
 // Partial sums of V[i]^* w for the kDotChunk basis vectors of one workgroup
 // row: each element of w is read once per chunk, and the loads of one element
@@ -521,6 +583,23 @@ hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipS
                            const InstDesc* insts, int ninst, const double* part_mid, int np_mid) {
   hipLaunchKernelGGL(k_cgf_step, dim3(ninst), dim3(kRedThreads), 0, s, part_out, nparts, st, insts, part_mid,
                      np_mid);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgf_alpha(const double* part_mid, int np_mid, CgState* st, hipStream_t s,
+                            const InstDesc* insts, int ninst) {
+  hipLaunchKernelGGL(k_cgf_alpha, dim3(ninst), dim3(kRedThreads), 0, s, part_mid, np_mid, st, insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgf_step_qf(const double* part_out, int nparts, CgState* st, hipStream_t s,
+                              const InstDesc* insts, int ninst) {
+  hipLaunchKernelGGL(k_cgf_step_qf, dim3(ninst), dim3(kRedThreads), 0, s, part_out, nparts, st, insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(double2* x, const double2* p, long long len, const CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_finish, dim3(ew_grid(len)), dim3(256), 0, s, x, p, len, st);
   return hipGetLastError();
 }
 

@@ -386,7 +386,8 @@ __device__ __forceinline__ int xpos(int e, int r) {
 }
 
 // R rows per workgroup; LDS tile[(c * R + r) * N + xpos(e, r)].
-template <int N1, int N2, int PART, bool CG = false, bool BT = false>
+// QF (with CG): the q-free schedule, whose last pass has already updated r.
+template <int N1, int N2, int PART, bool CG = false, bool BT = false, bool QF = false>
 __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const double2* __restrict__ y,
                                                       double2* __restrict__ fld, int R,
                                                       const int* skip, CgFuse cg,
@@ -433,7 +434,22 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
       double2 po[4], qo[4], ro[4], xo[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) po[b] = cg.p[b * n + f];
-      if (cg_iter > 0) {
+      if (QF && cg_iter > 0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          ro[b] = cg.r[b * n + f];
+          xo[b] = cg.x[b * n + f];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const long long o = b * n + f;
+          const double2 xv = make_double2(xo[b].x + cg_al * po[b].x, xo[b].y + cg_al * po[b].y);
+          const double2 pn = make_double2(ro[b].x + cg_be * po[b].x, ro[b].y + cg_be * po[b].y);
+          cg.x[o] = xv;
+          cg.p[o] = pn;
+          yv[b] = pn;
+        }
+      } else if (cg_iter > 0) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           qo[b] = cg.q[b * n + f];
@@ -487,7 +503,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   } else {
     for (int e = threadIdx.x; e < R * N; e += blockDim.x) synth(e);
   }
-  if (CG) {
+  if (CG && !QF) {
     block_sum_k<1>(rr_acc);
     if (threadIdx.x == 0) cg.part_in[blockIdx.x] = rr_acc[0];
   }
@@ -525,6 +541,9 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   }
 }
 
+// NOPQ (with CG): the q-free schedule; r = r - alpha q in place of q, with
+// alpha = rr / pap from the CG state (0 when pap is not positive: the step
+// kernel then stops the solve with a breakdown).
 template <int N1, int N2, int PART, bool CG = false, bool BT = false, bool NOPQ = false>
 __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
                                                      double2* __restrict__ out, int R,
@@ -543,6 +562,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
   constexpr int NP = N;
   constexpr int D = Split<N1, N2>::D;
   constexpr int F = (PART == kPartBoth) ? 6 : 3;
+  constexpr bool QF = CG && NOPQ;
   extern __shared__ double2 sm[];
   double2* twl = sm;
   double2* tile = sm + N;
@@ -550,6 +570,11 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
   const long long rows = (long long)g.n2 * g.n3;
   const long long row0 = (long long)blockIdx.x * R;
   const long long n = g.n;
+  double qf_al = 0.0;
+  if (QF) {
+    const double pap = cg.st->pap;
+    if (pap > 0.0 && isfinite(pap)) qf_al = cg.st->rr / pap;
+  }
   const int n2 = threadIdx.x % N2;
   const int r = (threadIdx.x / N2) % R;
   const int c = threadIdx.x / (N2 * R);
@@ -622,8 +647,10 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
         oa = csub(oa, cmul(B.pi2[cc], o));
         ob = cadd(ob, cmul(B.pi1[cc], o));
       }
-      out[f] = oa;
-      out[n + f] = ob;
+      if (!QF) {
+        out[f] = oa;
+        out[n + f] = ob;
+      }
     }
     if (PART == kPartBoth || PART == kPartQ) {
       const long long o0 = (PART == kPartBoth) ? 2 * n : 0;
@@ -635,9 +662,19 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
         oc = cadd(oc, cmulc(B.pi1[cc], o));
         od = cadd(od, cmulc(B.pi2[cc], o));
       }
-      out[o0 + f] = oc;
-      out[o0 + n + f] = od;
-      if (CG) {
+      if (!QF) {
+        out[o0 + f] = oc;
+        out[o0 + n + f] = od;
+      }
+      if (QF) {
+        const double2 qv[4] = {oa, ob, oc, od};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double2 rn = make_double2(rv[b].x - qf_al * qv[b].x, rv[b].y - qf_al * qv[b].y);
+          cg.r[b * n + f] = rn;
+          acc[0] += cabs2(rn);
+        }
+      } else if (CG) {
         const double2 qv[4] = {oa, ob, oc, od};
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -648,7 +685,11 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
       }
     }
   }
-  if (CG) {
+  if (QF) {
+    double a1[1] = {acc[0]};
+    block_sum_k<1>(a1);
+    if (threadIdx.x == 0) cg.part_out[blockIdx.x] = a1[0];
+  } else if (CG) {
     block_sum_k<3>(acc);
     if (threadIdx.x == 0) {
       cg.part_out[3 * blockIdx.x + 0] = acc[0];
@@ -751,6 +792,18 @@ hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int
   NSF_FAST_SWITCH(N, L_YZ)
 #undef L_YZ
   return hipGetLastError();
+}
+
+int fast_z_mid_pq_items(const Geom& g, int medium_kind, int P_want) {
+  const int N = g.n3;
+  FastCfg cfg;
+  if (!fast_cfg(N, cfg) || !g.mid_pairs || six_coupled(medium_kind)) return 0;
+  const size_t lmax = lds_limit() - 1024;
+  int P = pick_cols(g.n1, P_want);
+  while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax)) P /= 2;
+  if (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax) return 0;
+  const unsigned items = (unsigned)(3 * (g.n1 / P) * g.n2);
+  return items <= 2u * kMidSlots ? (int)items : 0;
 }
 
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
@@ -905,7 +958,7 @@ int fast_x_rows(const Geom& g) {
 
 hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg, double2* fld,
                                 const int* skip, int* nparts, hipStream_t s, const InstDesc* insts,
-                                int ninst) {
+                                int ninst, bool qfree) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -917,9 +970,15 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
   const dim3 block(6 * R * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + 6 * R * N);
 #define L_CGI(A, B)                                                                                  \
-  if (insts)                                                                                         \
+  if (insts && qfree)                                                                                \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true, true, true>), grid, block, lds, s, g, \
+                       t, (const double2*)nullptr, fld, R, skip, cg, insts);                         \
+  else if (insts)                                                                                    \
     hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true, true>), grid, block, lds, s, g, t,     \
                        (const double2*)nullptr, fld, R, skip, cg, insts);                            \
+  else if (qfree)                                                                                    \
+    hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true, false, true>), grid, block, lds, s, g, \
+                       t, (const double2*)nullptr, fld, R, skip, cg, insts);                         \
   else                                                                                               \
     hipLaunchKernelGGL((k_fx_inv_synth<A, B, kPartBoth, true>), grid, block, lds, s, g, t,           \
                        (const double2*)nullptr, fld, R, skip, cg, insts);

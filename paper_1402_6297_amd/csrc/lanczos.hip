@@ -121,6 +121,13 @@ int apply_all(std::vector<Group>& groups, hipStream_t s) {
 
 // One CG iteration of every unfinished run, enqueued on each run's plan stream
 // (single instances) or on s (groups sharing launches).
+// Whether the runs of G iterate in the q-free fused schedule.
+bool group_qfree(const Group& G) {
+  nsf_plan p0 = G.runs[0]->p;
+  if (G.fast) return fast_z_mid_pq_items(p0->geom, p0->medium_kind, p0->opt_mid_cols) > 0;
+  return cg_qfree(p0);
+}
+
 int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
   for (Group& G : groups) {
     const int na = (int)G.act.size();
@@ -136,15 +143,21 @@ int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
     const Geom& g = p0->geom;
     const InstDesc* d = G.d_desc;
     const CgFuse none{};
+    const bool qf = group_qfree(G);
     int np1 = 0, np5 = 0, npm = 0;
-    NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na));
-    NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na, qf));
+    if (!qf) NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na,
                                   nullptr, &npm));
+    if ((npm > 0) != qf) return set_error(p0, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
+    if (qf) NSF_HIP(p0, launch_cgf_alpha(nullptr, npm, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, npm > 0));
-    NSF_HIP(p0, launch_cgf_step(nullptr, np5, nullptr, s, d, na, nullptr, npm));
+    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, qf));
+    if (qf)
+      NSF_HIP(p0, launch_cgf_step_qf(nullptr, np5, nullptr, s, d, na));
+    else
+      NSF_HIP(p0, launch_cgf_step(nullptr, np5, nullptr, s, d, na, nullptr, npm));
   }
   return NSF_OK;
 }
@@ -208,6 +221,14 @@ int cg_graph_ready(CgGraph& cg, std::vector<Group>& groups, std::vector<Run*>& a
   cg.sig = sig;
   cg.captures += 1;
   return NSF_OK;
+}
+
+// Whether run r iterates in the q-free fused schedule (by its group).
+bool qfree_of(const std::vector<Group>& groups, const Run* r) {
+  for (const Group& G : groups)
+    for (const Run* q : G.runs)
+      if (q == r) return group_qfree(G);
+  return false;
 }
 
 // w = A_r^{-1} bv by CG for every unfinished run, all advancing together.
@@ -286,7 +307,8 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
       const CgState& h = *act[i]->p->h_state;
       if (h.done) continue;
       all = false;
-      next = std::max(next, cg_predict(h, rr_prev[i], it_prev[i], cg_fusable(act[i]->p)));
+      const bool lag = cg_fusable(act[i]->p) && !qfree_of(groups, act[i]);
+      next = std::max(next, cg_predict(h, rr_prev[i], it_prev[i], lag));
       rr_prev[i] = h.rr;
       it_prev[i] = h.iter;
     }
@@ -300,6 +322,8 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
     r->st.matvecs += h.iter;
     if (h.status == NSF_E_BREAKDOWN)
       return set_error(r->p, NSF_E_BREAKDOWN, "CG breakdown: p^* A_r p <= 0 or not finite");
+    if (qfree_of(groups, r))  // the final x = x + alpha p (ws has drained)
+      NSF_HIP(r->p, launch_cg_finish(r->w, r->p->d_cg + r->len, r->len, r->p->d_state, s));
   }
   return NSF_OK;
 }
@@ -452,13 +476,15 @@ int lock_in(Run* r, hipStream_t s) {
 
 // Run every instance to convergence (or its restart cap) in lock step.
 int run_engine(std::vector<Run*>& runs, hipStream_t s) {
-  // groups of equal grid shape and pass configuration
+  // groups of equal grid shape, pass configuration and z-pass kernel (media
+  // coupling all six fields cannot share the field-pair launches)
   std::map<std::tuple<int, int, int, double, double, int, int>, int> key;
   std::vector<Group> groups;
   for (Run* r : runs) {
     const Geom& g = r->p->geom;
     auto k = std::make_tuple(g.n1, g.n2, g.n3, g.alpha, g.beta, r->p->opt_fft_path,
-                             r->p->opt_mid_cols * 2048 + g.mid_pairs * 1024 + g.x_rows * 32 + g.yz_cols);
+                             (six_coupled(r->p->medium_kind) ? 1 << 20 : 0) + r->p->opt_mid_cols * 2048 +
+                                 g.mid_pairs * 1024 + g.x_rows * 32 + g.yz_cols);
     if (!key.count(k)) {
       key[k] = (int)groups.size();
       groups.emplace_back();

@@ -179,6 +179,7 @@ struct CgState {
   int done;         // nonzero: every CG kernel exits at once
   int status;       // NSF_OK / NSF_NOT_CONVERGED / NSF_E_BREAKDOWN
   int pad[3];
+  double pap;       // p^* A_r p of the current direction (q-free fused schedule)
 };
 
 // Vectors and device scalars of a CG solve whose recurrences are fused into
@@ -212,13 +213,26 @@ struct InstDesc {
 // previous iteration), writes them and the per-workgroup |r|^2, then
 // synthesises from p exactly like launch_fast_x_inv_synth.  Returns the
 // number of workgroups through *nparts.
+//
+// q-free form (qfree = true), used when the fused z pass sums p^* A_r p: the
+// first pass forms x = x + alpha p, p = r + beta p only (r was already updated
+// by the last pass) and writes no partial sums.
 int fast_x_rows(const Geom& g);
 hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg, double2* fld,
                                 const int* skip, int* nparts, hipStream_t s,
-                                const InstDesc* insts = nullptr, int ninst = 1);
+                                const InstDesc* insts = nullptr, int ninst = 1, bool qfree = false);
+// Workgroups of the fused z pass that sum p^* A_r p for this geometry and
+// medium kind (0: that pass sums nothing, so the q-free schedule is off).
+int fast_z_mid_pq_items(const Geom& g, int medium_kind, int P_want);
+// The same decision for a plan's own z pass (pass_z_mid).
+int z_mid_pq_items(nsf_plan p);
+bool cg_qfree(nsf_plan p);
 // Last pass: q = projection of the forward x transform (written to cg.q) and
 // the per-workgroup partial sums of p^*q, |q|^2, r^*q.
-// pq_done: the fused z pass already produced p^* A_r p, so p is not read here.
+// pq_done (the q-free form): the fused z pass already produced p^* A_r p and
+// launch_cgf_alpha turned it into cg.st->pap; the pass forms q on the fly, sets
+// r = r - alpha q with alpha = rr / pap, writes r (not q) and the per-workgroup
+// |r|^2.
 hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
                                const int* skip, int* nparts, hipStream_t s,
                                const InstDesc* insts = nullptr, int ninst = 1, bool pq_done = false);
@@ -231,6 +245,16 @@ hipError_t launch_cgf_check(const double* part_in, int nparts, CgState* st, hipS
 hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipStream_t s,
                            const InstDesc* insts = nullptr, int ninst = 1,
                            const double* part_mid = nullptr, int np_mid = 0);
+// q-free schedule: after the fused z pass, st->pap = sum of its partials; after
+// the last pass, |r|^2 from its partials, alpha = rr / pap, beta = |r_new|^2 / rr,
+// the convergence test, iter + 1.  launch_cg_finish then applies the pending
+// x = x + alpha p of the final iteration once the state is done (not after a
+// breakdown).
+hipError_t launch_cgf_alpha(const double* part_mid, int np_mid, CgState* st, hipStream_t s,
+                            const InstDesc* insts = nullptr, int ninst = 1);
+hipError_t launch_cgf_step_qf(const double* part_out, int nparts, CgState* st, hipStream_t s,
+                              const InstDesc* insts = nullptr, int ninst = 1);
+hipError_t launch_cg_finish(double2* x, const double2* p, long long len, const CgState* st, hipStream_t s);
 
 // partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
 hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,

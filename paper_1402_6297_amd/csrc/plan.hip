@@ -115,6 +115,13 @@ hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post
   return launch_yz_pass(g, p->ax[axis], p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
 }
 
+int z_mid_pq_items(nsf_plan p) {
+  const Geom& g = p->geom;
+  if (p->opt_fft_path == 2 && wave_mid_ok(g) && !six_coupled(p->medium_kind)) return 0;
+  if (p->opt_fft_path != 1 && fast_axis(g.n3)) return fast_z_mid_pq_items(g, p->medium_kind, p->opt_mid_cols);
+  return 0;
+}
+
 hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid, int* np_mid) {
   const Geom& g = p->geom;
   if (np_mid) *np_mid = 0;

@@ -134,15 +134,21 @@ int cg_iteration(nsf_plan p, double2* x, bool fused) {
   double2* q = pp + len;
   if (fused) {
     const CgFuse cgf = cg_fuse_of(p, x);
+    const bool qf = z_mid_pq_items(p) > 0;
     int np1 = 0, np5 = 0;
-    NSF_HIP(p, launch_fast_cg_first(p->geom, p->tabs, cgf, p->d_fields, skip, &np1, s));
-    NSF_HIP(p, launch_cgf_check(cgf.part_in, np1, st, s));
+    NSF_HIP(p, launch_fast_cg_first(p->geom, p->tabs, cgf, p->d_fields, skip, &np1, s, nullptr, 1, qf));
+    if (!qf) NSF_HIP(p, launch_cgf_check(cgf.part_in, np1, st, s));
     NSF_HIP(p, pass_yz(p, 1, +1, 6, p->d_fields, 0, 0, skip));
     int npm = 0;
     NSF_HIP(p, pass_z_mid(p, p->d_fields, skip, cgf.part_mid, &npm));
+    if ((npm > 0) != qf) return set_error(p, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
+    if (qf) NSF_HIP(p, launch_cgf_alpha(cgf.part_mid, npm, st, s));
     NSF_HIP(p, pass_yz(p, 1, -1, 6, p->d_fields, 0, 0, skip));
-    NSF_HIP(p, launch_fast_cg_last(p->geom, p->tabs, cgf, p->d_fields, skip, &np5, s, nullptr, 1, npm > 0));
-    NSF_HIP(p, launch_cgf_step(cgf.part_out, np5, st, s, nullptr, 1, cgf.part_mid, npm));
+    NSF_HIP(p, launch_fast_cg_last(p->geom, p->tabs, cgf, p->d_fields, skip, &np5, s, nullptr, 1, qf));
+    if (qf)
+      NSF_HIP(p, launch_cgf_step_qf(cgf.part_out, np5, st, s));
+    else
+      NSF_HIP(p, launch_cgf_step(cgf.part_out, np5, st, s, nullptr, 1, cgf.part_mid, npm));
     return NSF_OK;
   }
   const int nparts = reduce_parts_for(len);
@@ -156,8 +162,12 @@ int cg_iteration(nsf_plan p, double2* x, bool fused) {
   return NSF_OK;
 }
 
+// Fused CG of plan p in the q-free schedule (its z pass sums p^* A_r p).
+bool cg_qfree(nsf_plan p) { return cg_fusable(p) && z_mid_pq_items(p) > 0; }
+
 // Predicted CG iterations still needed, from the convergence rate observed
-// between two reads of the state.
+// between two reads of the state (fused: one more, as the fused schedule tests
+// convergence one pass later).
 int cg_predict(const CgState& h, double rr_prev, int it_prev, bool fused) {
   int next = 8;
   if (rr_prev > 0 && h.rr > 0 && h.rr < rr_prev && h.iter > it_prev) {
@@ -185,6 +195,7 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
   // ride in the first and last FFT pass of every A_r apply.
   const Geom& g = p->geom;
   const bool fused = cg_fusable(p);
+  const bool qf = fused && cg_qfree(p);
   (void)nparts;
   (void)g;
   int chunk = 4;
@@ -199,10 +210,11 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
     NSF_HIP(p, hipStreamSynchronize(s));
     const CgState& h = *p->h_state;
     if (h.done) break;
-    chunk = cg_predict(h, rr_prev, it_prev, fused);
+    chunk = cg_predict(h, rr_prev, it_prev, fused && !qf);
     rr_prev = h.rr;
     it_prev = h.iter;
   }
+  if (qf) NSF_HIP(p, launch_cg_finish(x, pp, len, st, s));
   const CgState& h = *p->h_state;
   if (iters) *iters = h.iter;
   if (relres) *relres = (h.bb > 0) ? std::sqrt(h.rr / h.bb) : 0.0;

@@ -520,6 +520,54 @@ def test_ortho_gate_same_eigenpairs(batched, res_tol):
     assert np.abs(om1 - om0).max() <= 1e-10 * om0.max()
 
 
+def test_qfree_and_classic_fused_cg_agree_32():
+    """The fused CG runs in the q-free schedule when the field-pair z pass sums
+    p^* A_r p (r updated in the last pass, no q vector), else in the classic one
+    (q stored, beta by expansion).  Both solve to rtol with the same iteration
+    count (+-1) and agree to the conditioning of the tolerance."""
+    grid, k = (32, 32, 32), (0.1, 0.2, 0.3)
+    n = 32 ** 3
+    eps, gam = media.sphere_chiral(32)
+    b = dev(media.random_vector(4 * n, 8))
+    xs, its = [], []
+    for pairs in (1, 0):
+        with nsf.Plan(grid, k) as P:
+            P.set_option(nsf.NSF_OPT_MID_PAIRS, pairs)
+            P.set_chiral(eps, gam)
+            x = torch.empty_like(b)
+            st, it, rr = nsf.nsf_cg_solve(P.handle, b, x, rtol=1e-11)
+            assert st == nsf.NSF_OK and rr <= 1e-11
+            xs.append(host(x))
+            its.append(it)
+            Ax = torch.empty_like(b)
+            P.Ar(x, Ax)  # the true residual of the returned x
+            assert np.linalg.norm(host(Ax) - host(b)) <= 2e-11 * np.linalg.norm(host(b))
+    assert abs(its[0] - its[1]) <= 1
+    assert rel(xs[0], xs[1]) < 1e-8
+
+
+def test_batch_mixing_general_and_chiral_media_16():
+    """A batch whose instances share a grid but not the z-pass kernel (a general
+    tensor medium next to chiral ones) gives each instance its own solution."""
+    grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
+    chi = media.sphere_chiral(16)
+    gen = media.random_general(16, seed=3)
+    ref = []
+    for i in range(3):
+        with nsf.Plan(grid, k) as P:
+            (P.set_tensor(*gen) if i == 1 else P.set_chiral(*chi))
+            st, om, res, _ = P.eigs(4, res_tol=1e-10, cg_rtol=1e-12, seed=1000003 * i)
+            assert st == nsf.NSF_OK
+            ref.append(om)
+    with nsf.Batch([grid] * 3, [k] * 3) as B:
+        for i in range(3):
+            (B.set_tensor(i, *gen) if i == 1 else B.set_chiral(i, *chi))
+        st, om, res, stats, _ = B.eigs(4, res_tol=1e-10, cg_rtol=1e-12)
+    assert st == nsf.NSF_OK and res.max() <= 1e-10
+    for i in range(3):
+        assert np.abs(om[i] - ref[i]).max() <= 1e-10 * ref[i].max()
+
+
 # ------------------------------------------------------------ general media
 
 GENERAL_CASES = [((4, 4, 4), (0.1, 0.2, 0.3)), ((16, 12, 10), (0.3, 0.1, 0.2)),
