@@ -132,7 +132,9 @@ enum {
                             applies it; converged pairs meet the residual
                             tolerance either way                             */
   NSF_OPT_GMRES_RESTART = 10, /* restart length of the GMRES inner solves of
-                            nsf_eigs_nfsep, 4..500 (default 40)             */
+                            nsf_eigs_nfsep, 4..500 (default 12: at 128^3 the
+                            classical Gram-Schmidt over a long basis costs
+                            more than the extra iterations of restarting)  */
   NSF_OPT_MEDIUM_PALETTE = 11 /* general and NFSEP media, read by the next
                             nsf_set_medium_tensor / nsf_set_medium_nfsep: 1
                             stores the distinct voxel factors once plus a
@@ -280,7 +282,7 @@ int nsf_apply_nfsep(nsf_plan plan, const nsf_c128* y4n, nsf_c128* out4n);
  * diag(Sigma_r, Sigma_r) (K = Sigma'^{1/2} (i J4) Kern Sigma'^{1/2}).  GMRES
  * starts from zero and stops when the recomputed residual of that system is
  * <= rtol times its right-hand side (relres, host), or after maxit iterations
- * (<= 0: 2000).  restart <= 0: 40.  b, x device, distinct.  Returns NSF_OK or
+ * (<= 0: 2000).  restart <= 0: 12.  b, x device, distinct.  Returns NSF_OK or
  * NSF_NOT_CONVERGED; allocates and frees the GMRES basis ((restart + 1) 4n
  * complex values).  Synchronises.
  */

@@ -473,7 +473,7 @@ int nsf_nfsep_solve(nsf_plan p, const nsf_c128* b, nsf_c128* x, double rtol, int
   if ((const void*)b == (const void*)x) return set_error(p, NSF_E_ARG, "b and x must be distinct");
   if (!(rtol > 0.0)) return set_error(p, NSF_E_ARG, "rtol must be > 0");
   if (p->medium_kind != kMedNfsep) return set_error(p, NSF_E_STATE, "no NFSEP medium set");
-  const int R = restart > 0 ? std::min(restart, 500) : 40;
+  const int R = restart > 0 ? std::min(restart, 500) : 12;
   if (maxit <= 0) maxit = 2000;
   int rc = ensure_device(p);
   if (rc) return rc;

@@ -368,7 +368,7 @@ struct nsf_plan_s {
   int opt_cg_start = 1;     // eigensolver CG starts from the Galerkin solution in span(V)
   int opt_verify = 0;       // multiplicity checks after convergence (nsf_eigs)
   int opt_ortho_gate = 1;   // skip negligible Gram-Schmidt updates on the device
-  int opt_gmres_restart = 40;  // GMRES restart length of the NFSEP eigensolver
+  int opt_gmres_restart = 12;  // GMRES restart length of the NFSEP eigensolver
   int opt_palette = 1;      // general / NFSEP media: palette of distinct voxel factors
 
   std::string last_error;
