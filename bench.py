@@ -509,6 +509,8 @@ def main():
     ap.add_argument("--gamma-sweep", action="store_true", help="CG iterations against chirality (64^3)")
     ap.add_argument("--nfsep", type=int, default=64, metavar="N",
                     help="NFSEP leg (lossy sphere, shift-invert Arnoldi) at N^3; 0 skips it")
+    ap.add_argument("--nfsep-only", action="store_true",
+                    help="run only the NFSEP leg (at --nfsep N) and print its JSON")
     ap.add_argument("--grad", type=int, default=0, metavar="NVOX",
                     help="gradient leg at 64^3: kernel cost and central differences at NVOX voxels")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -535,6 +537,9 @@ def main():
     from paper_1402_6297_amd import media, nsf
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.nfsep_only:
+        print(json.dumps(nfsep_leg(args.nfsep or 128)), flush=True)
+        return
     w = WORKLOADS[args.workload]
     grid, k = w["grid"], w["k"]
     n = grid[0] * grid[1] * grid[2]
