@@ -125,12 +125,13 @@ enum {
                             when nothing changed.  Needed for spectra with
                             multiple eigenvalues (symmetric media at symmetric
                             k-points); not applied by nsf_batch_eigs           */
-  NSF_OPT_ORTHO_GATE = 9, /* eigensolver Gram-Schmidt: 1 skips the basis update
-                            of a new Lanczos direction on the device when its
-                            A_r-cosine with every basis vector is at most
-                            1e-2 res_tol, capped at 1e-10 (default), 0 always
-                            applies it; converged pairs meet the residual
-                            tolerance either way                             */
+  NSF_OPT_ORTHO_GATE = 9, /* eigensolver Gram-Schmidt: 1 removes from a new
+                            Lanczos direction only its components whose
+                            A_r-cosine with a basis vector exceeds 1e-2
+                            res_tol, capped at 1e-10, reading just those
+                            basis columns (default); 0 always runs the full
+                            classical pass; converged pairs meet the
+                            residual tolerance either way                    */
   NSF_OPT_GMRES_RESTART = 10, /* restart length of the GMRES inner solves of
                             nsf_eigs_nfsep, 4..500 (default 12: at 128^3 the
                             classical Gram-Schmidt over a long basis costs

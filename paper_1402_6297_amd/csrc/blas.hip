@@ -375,6 +375,40 @@ __global__ __launch_bounds__(kRedThreads) void k_multi_dot(const double2* __rest
   }
 }
 
+// The same for two right-hand sides: partials of V[i]^* w1 (rows 0..m) and
+// V[i]^* w2 (rows m..2m), each basis element read once for both.
+__global__ __launch_bounds__(kRedThreads) void k_multi_dot2(const double2* __restrict__ V, long long ld,
+                                                            int m, const double2* __restrict__ w1,
+                                                            const double2* __restrict__ w2, long long len,
+                                                            double2* partial) {
+  const int i0 = blockIdx.y * kDotChunk;
+  const int cnt = min(kDotChunk, m - i0);
+  double2 a1[kDotChunk], a2[kDotChunk];
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) a1[c] = a2[c] = make_double2(0, 0);
+  const double2* Vc = V + (long long)i0 * ld;
+  for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < len;
+       e += (long long)gridDim.x * kRedThreads) {
+    const double2 x1 = w1[e], x2 = w2[e];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c)
+      if (c < cnt) {
+        const double2 v = Vc[c * ld + e];
+        a1[c] = cadd(a1[c], cmulc(v, x1));
+        a2[c] = cadd(a2[c], cmulc(v, x2));
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) {
+    const double2 s1 = block_sum(a1[c]);
+    const double2 s2 = block_sum(a2[c]);
+    if (threadIdx.x == 0 && c < cnt) {
+      partial[(long long)(i0 + c) * gridDim.x + blockIdx.x] = s1;
+      partial[(long long)(m + i0 + c) * gridDim.x + blockIdx.x] = s2;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kRedThreads) void k_multi_dot_final(const double2* partial, int nparts,
                                                                  double2* out) {
   const double2 s = fold_partials(partial + (long long)blockIdx.x * nparts, nparts);
@@ -614,6 +648,81 @@ hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2
   const dim3 grid((unsigned)nb, rows);
   hipLaunchKernelGGL(k_multi_dot, grid, dim3(kRedThreads), 0, s, V, ld, m, w, len, partial);
   hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(kRedThreads), 0, s, partial, (int)nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_dot2(const double2* V, long long ld, int m, const double2* w1, const double2* w2,
+                             long long len, double2* partial, double2* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int rows = (m + kDotChunk - 1) / kDotChunk;
+  long long nb = std::min<long long>((len + kRedThreads - 1) / kRedThreads, 4096 / rows);
+  nb = std::min<long long>(nb, kPartialSlots / (2 * m));
+  if (nb < 1) nb = 1;
+  const dim3 grid((unsigned)nb, rows);
+  hipLaunchKernelGGL(k_multi_dot2, grid, dim3(kRedThreads), 0, s, V, ld, m, w1, w2, len, partial);
+  hipLaunchKernelGGL(k_multi_dot_final, dim3(2 * m), dim3(kRedThreads), 0, s, partial, (int)nb, out);
+  return hipGetLastError();
+}
+
+// z = b - r - sum_k c_k AV_{idx_k}: the image A_r x of a CG solution from its
+// right-hand side b, final residual r and the projected start (c as for
+// launch_cg_init: m coefficients, then the m indices as doubles in .x).
+__global__ void k_cg_image(const double2* __restrict__ b, const double2* __restrict__ r,
+                           const double2* __restrict__ AV, long long ld, int m, const double2* __restrict__ c,
+                           double2* __restrict__ z, long long len) {
+  __shared__ double2 cs[512];
+  __shared__ int ix[512];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    cs[i] = c[i];
+    ix[i] = (int)c[m + i].x;
+  }
+  __syncthreads();
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x) {
+    double2 v = csub(b[i], r[i]);
+#pragma unroll 4
+    for (int j = 0; j < m; ++j) v = csub(v, cmul(cs[j], AV[ix[j] * ld + i]));
+    z[i] = v;
+  }
+}
+
+// w -= sum_k c_k V_{idx_k} and z -= sum_k c_k V2_{idx_k} (c: m coefficients, then
+// the m indices as doubles in .x): a Gram-Schmidt update over a few basis columns.
+__global__ void k_sparse_axpy2(const double2* __restrict__ V, const double2* __restrict__ V2, long long ld,
+                               int m, const double2* __restrict__ c, double2* __restrict__ w,
+                               double2* __restrict__ z, long long len) {
+  __shared__ double2 cs[512];
+  __shared__ int ix[512];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    cs[i] = c[i];
+    ix[i] = (int)c[m + i].x;
+  }
+  __syncthreads();
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x) {
+    double2 a = w[i], b = z[i];
+#pragma unroll 4
+    for (int j = 0; j < m; ++j) {
+      a = csub(a, cmul(cs[j], V[ix[j] * ld + i]));
+      b = csub(b, cmul(cs[j], V2[ix[j] * ld + i]));
+    }
+    w[i] = a;
+    z[i] = b;
+  }
+}
+
+hipError_t launch_sparse_axpy2(const double2* V, const double2* V2, long long ld, int m, const double2* c,
+                               double2* w, double2* z, long long len, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (m > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sparse_axpy2, dim3(ew_grid(len)), dim3(256), 0, s, V, V2, ld, m, c, w, z, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_image(const double2* b, const double2* r, const double2* AV, long long ld, int m,
+                           const double2* c, double2* z, long long len, hipStream_t s) {
+  if (m < 0 || m > 512 || (m > 0 && (!AV || !c))) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_image, dim3(ew_grid(len)), dim3(256), 0, s, b, r, AV, ld, m, c, z, len);
   return hipGetLastError();
 }
 

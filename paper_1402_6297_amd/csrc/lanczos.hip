@@ -38,6 +38,7 @@ struct Run {
   int nb = 0;
   std::vector<double> theta, eta;
   double start_h2 = 0;  // |h|^2 of the projected CG start of the current step
+  int start_m = 0;       // basis columns in that start (coefficients and indices in d_coef)
   int nlock = 0;        // V[0..nlock) (with A_r V) hold A_r-orthonormal vectors to keep
   std::vector<double2> Sk;
   nsf_stats st{};
@@ -267,6 +268,7 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
       for (int j = 0; j < m; ++j) hc[m + j] = hc[512 + j];
       if (m) NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * 2 * m, hipMemcpyHostToDevice, s));
     }
+    r->start_m = m;
     NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, p->d_cg + r->len, r->len, p->d_partial, p->d_state,
                               r->cg_rtol, 5000, s, m ? r->AV : nullptr, r->len, m, m ? p->d_coef : nullptr));
   }
@@ -584,38 +586,124 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
     if ((rc = cg_all(groups, act, s, &cg_graph))) return fail(rc);
     t_cg += ms_since(t0);
     t0 = clk::now();
-    if ((rc = apply_all(groups, s))) return fail(rc);
+    // z = A_r w from the CG's right-hand side and final residual: CG solved
+    // A_r w = bv - (A_r V) h from w = 0 (projected start), so A_r w =
+    // bv - (A_r V) h - r, with h and its basis indices still in d_coef.  Then
+    // B_r w into bv and one pass over V for both V^* z (the A_r inner products
+    // with the basis) and V^* B_r w (the new column of H), and the norms
+    // w^* A_r w, w^* B_r w.
     for (Run* r : act) {
-      r->st.matvecs += 1;
-      if ((rc = dot_async(r->p, r->w, r->z, r->len, 0))) return fail(rc);  // norm before
-      if ((rc = ortho_pass(r, r->p->opt_ortho_gate ? 0 : -1))) return fail(rc);
+      nsf_plan p = r->p;
+      NSF_HIP(p, launch_cg_image(r->bv, p->d_cg, r->AV, r->len, r->start_m, p->d_coef, r->z, r->len, s));
+      NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, r->w, r->bv, nullptr, s));
+      NSF_HIP(p, launch_multi_dot2(r->V, r->len, r->nb, r->z, r->bv, r->len, p->d_partial, p->d_coef, s));
+      NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_coef, sizeof(double2) * 2 * r->nb, hipMemcpyDeviceToHost, s));
+      if ((rc = dot_async(p, r->w, r->z, r->len, 0))) return fail(rc);   // ||w||_A^2
+      if ((rc = dot_async(p, r->w, r->bv, r->len, 1))) return fail(rc);  // w^* B_r w
     }
     NSF_HIP(act[0]->p, hipStreamSynchronize(s));
-    bool again = false;
-    std::vector<double> before(act.size());
-    for (size_t i = 0; i < act.size(); ++i) {
-      nsf_plan p = act[i]->p;
-      before[i] = p->h_res[0].x;
-      if (p->h_res[1].x <= 0.5 * before[i]) {  // second pass needed
-        before[i] = p->h_res[1].x;
-        if ((rc = ortho_pass(act[i]))) return fail(rc);
-        again = true;
+    // Sparse Gram-Schmidt: only the coefficients c_i = v_i^* A_r w above
+    // ortho_skip_cos ||w||_A are removed (usually none or the few basis columns
+    // the projected start left out), reading just those columns of V and A_r V;
+    // the H column follows by linearity, V^* B_r (w - V_S c_S) = g - H[:, S] c_S,
+    // with H exact on the host.  A second full pass (and the column recomputed)
+    // only when the update removes more than half of ||w||_A^2.
+    std::vector<Run*> slow, sparse;
+    std::vector<std::vector<double2>> cg_host(act.size());
+    std::vector<std::vector<int>> sel(act.size());
+    std::vector<double> h0s(act.size());
+    auto admit_fast = [&](Run* r, const std::vector<double2>& cgv, const std::vector<int>& S, double h1,
+                          double wbw) -> int {
+      nsf_plan p = r->p;
+      const int nb = r->nb;
+      const double sc = 1.0 / std::sqrt(h1);
+      double2* hc = p->h_res + 64;
+      for (int i = 0; i < nb; ++i) {
+        double2 gi = cgv[nb + i];
+        for (int k : S) gi = csub(gi, cmul(r->Hat(i, k), cgv[k]));
+        hc[i] = cscale(gi, sc);
       }
-    }
-    if (again) NSF_HIP(act[0]->p, hipStreamSynchronize(s));
-    for (size_t i = 0; i < act.size(); ++i) {
-      Run* r = act[i];
-      // invariant subspace: nothing of A_r^{-1} B_r v is left outside span(V)
-      if (!(r->p->h_res[1].x > 1e-20 * (r->p->h_res[0].x + r->start_h2))) {
-        if ((rc = refresh_direction(r, s))) return fail(rc);
-      }
-      if ((rc = admit_enqueue(r, r->nb, r->p->h_res[1].x))) return fail(rc);
-    }
-    NSF_HIP(act[0]->p, hipStreamSynchronize(s));
-    for (Run* r : act) {
-      admit_finish(r, r->nb);
+      hc[nb] = make_double2(wbw / h1, 0.0);
+      admit_finish(r, nb);
+      NSF_HIP(p, launch_scale_copy(r->w, r->V + (size_t)nb * r->len, sc, 0.0, r->len, s));
+      NSF_HIP(p, launch_scale_copy(r->z, r->AV + (size_t)nb * r->len, sc, 0.0, r->len, s));
+      NSF_HIP(p, launch_scale_copy(r->bv, r->bv, sc, 0.0, r->len, s));  // B_r of the new vector
       r->nb += 1;
       r->st.lanczos_steps += 1;
+      r->st.ortho_passes += 1;
+      return NSF_OK;
+    };
+    for (size_t a = 0; a < act.size(); ++a) {
+      Run* r = act[a];
+      nsf_plan p = r->p;
+      const int nb = r->nb;
+      const double h0 = p->h_res[0].x, wbw = p->h_res[1].x;
+      h0s[a] = h0;
+      const double tau = ortho_skip_cos(r);
+      cg_host[a].assign(p->h_res + 64, p->h_res + 64 + 2 * nb);
+      for (int i = 0; i < nb; ++i)
+        if (cabs2(cg_host[a][i]) > tau * tau * h0) sel[a].push_back(i);
+      const bool ok = p->opt_ortho_gate && h0 > 0.0 && std::isfinite(h0) && std::isfinite(wbw) &&
+                      h0 > 1e-20 * (h0 + r->start_h2) && (int)sel[a].size() <= 64;
+      if (!ok) {
+        slow.push_back(r);
+      } else if (sel[a].empty()) {
+        if ((rc = admit_fast(r, cg_host[a], sel[a], h0, wbw))) return fail(rc);
+      } else {
+        double2* hc = p->h_res + 64;  // staging: coefficients, then indices
+        const int ms = (int)sel[a].size();
+        for (int k = 0; k < ms; ++k) {
+          hc[k] = cg_host[a][sel[a][k]];
+          hc[ms + k] = make_double2((double)sel[a][k], 0.0);
+        }
+        NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * 2 * ms, hipMemcpyHostToDevice, s));
+        NSF_HIP(p, launch_sparse_axpy2(r->V, r->AV, r->len, ms, p->d_coef, r->w, r->z, r->len, s));
+        NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, r->w, r->bv, nullptr, s));
+        if ((rc = dot_async(p, r->w, r->z, r->len, 2))) return fail(rc);   // ||w||_A^2 after
+        if ((rc = dot_async(p, r->w, r->bv, r->len, 3))) return fail(rc);  // w^* B_r w after
+        sparse.push_back(r);
+      }
+    }
+    if (!sparse.empty()) {
+      NSF_HIP(sparse[0]->p, hipStreamSynchronize(s));
+      for (Run* r : sparse) {
+        const size_t a = std::find(act.begin(), act.end(), r) - act.begin();
+        nsf_plan p = r->p;
+        const double h1 = p->h_res[2].x, wbw1 = p->h_res[3].x;
+        if (!(h1 > 0.5 * h0s[a]) || !std::isfinite(h1) || !std::isfinite(wbw1)) {
+          p->h_res[0].x = h1;  // the full path below starts from the updated w
+          slow.push_back(r);
+          continue;
+        }
+        if ((rc = admit_fast(r, cg_host[a], sel[a], h1, wbw1))) return fail(rc);
+      }
+    }
+    if (!slow.empty()) {
+      for (Run* r : slow)
+        if ((rc = ortho_pass(r))) return fail(rc);  // norm before: slot 0 above
+      NSF_HIP(slow[0]->p, hipStreamSynchronize(s));
+      bool again = false;
+      for (Run* r : slow) {
+        nsf_plan p = r->p;
+        if (p->h_res[1].x <= 0.5 * p->h_res[0].x) {  // second pass needed
+          if ((rc = ortho_pass(r))) return fail(rc);
+          again = true;
+        }
+      }
+      if (again) NSF_HIP(slow[0]->p, hipStreamSynchronize(s));
+      for (Run* r : slow) {
+        // invariant subspace: nothing of A_r^{-1} B_r v is left outside span(V)
+        if (!(r->p->h_res[1].x > 1e-20 * (r->p->h_res[0].x + r->start_h2))) {
+          if ((rc = refresh_direction(r, s))) return fail(rc);
+        }
+        if ((rc = admit_enqueue(r, r->nb, r->p->h_res[1].x))) return fail(rc);
+      }
+      NSF_HIP(slow[0]->p, hipStreamSynchronize(s));
+      for (Run* r : slow) {
+        admit_finish(r, r->nb);
+        r->nb += 1;
+        r->st.lanczos_steps += 1;
+      }
     }
     t_orth += ms_since(t0);
     t0 = clk::now();

@@ -278,6 +278,17 @@ hipError_t launch_cg_p(double2* p, const double2* r, long long len, CgState* st,
 // c[i] = sum_e conj(V_i[e]) w[e], i < m, written as m complex values to out.
 hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2* w, long long len,
                             double2* partial, double2* out, hipStream_t s);
+// out[0..m) = V^* w1 and out[m..2m) = V^* w2 in one pass over V (m <= 256).
+hipError_t launch_multi_dot2(const double2* V, long long ld, int m, const double2* w1, const double2* w2,
+                             long long len, double2* partial, double2* out, hipStream_t s);
+// z = b - r - sum_k c_k AV_{idx_k} (c, idx laid out as for launch_cg_init; m <= 512):
+// A_r x for a CG solution x of A_r x = b started from the projected guess.
+hipError_t launch_cg_image(const double2* b, const double2* r, const double2* AV, long long ld, int m,
+                           const double2* c, double2* z, long long len, hipStream_t s);
+// w -= sum_k c_k V_{idx_k}, z -= sum_k c_k V2_{idx_k} (c: m coefficients then m
+// indices as doubles in .x, device; m <= 512).
+hipError_t launch_sparse_axpy2(const double2* V, const double2* V2, long long ld, int m, const double2* c,
+                               double2* w, double2* z, long long len, hipStream_t s);
 // w -= sum_i c[i] V_i and, if V2 is given, z -= sum_i c[i] V2_i  (c on device, m <= 512).
 // With a gate (device, ||w||^2 in gate->x) nothing is written when
 // max_i |c[i]|^2 <= tau2 ||w||^2.
