@@ -145,6 +145,17 @@ enum {
 };
 
 /*
+ * Environment switches (read at each call):
+ *   NSF_TRACE=1|stderr|<file>  one JSON line per finished nsf_eigs, per instance
+ *                              of nsf_batch_eigs and per nsf_eigs_nfsep (status,
+ *                              counters, phase times, largest residual);
+ *   NSF_SYNC_CHECK=1           synchronise the device after every HIP call the
+ *                              library checks and report the first failing call
+ *                              (debugging; graph capture of CG iterations off);
+ *   NSF_TUNE_CACHE=<file>      autotune results kept per grid shape and medium.
+ */
+
+/*
  * Device bytes per voxel that an A_r / Kern apply reads for the medium: 16
  * for chiral and pseudochiral media ((eps, gamma)), 336 (general) or 576
  * (NFSEP) for factors stored per voxel, 2 with a palette; palette (nullable)
@@ -180,6 +191,9 @@ typedef struct {
   int tried;
 } nsf_tune;
 int nsf_plan_autotune(nsf_plan plan, int reps, nsf_tune* result);
+/* With NSF_TUNE_CACHE naming a text file, nsf_plan_autotune first looks up the
+ * grid shape and medium kind there (a hit applies the stored tiling, reports
+ * tried = 0 and times nothing) and appends each new result. */
 
 /*
  * Caller-provided workspace (for example from PyTorch's caching allocator).
@@ -308,7 +322,8 @@ int nsf_nfsep_solve(nsf_plan plan, const nsf_c128* b, nsf_c128* x, double rtol,
  * device 4n x nev: the unit vectors x = Sigma'^{1/2} y, the scaled vectors
  * Algorithm 1 hands to field recovery, so nsf_fields(x) gives E and H),
  * resid_host (nullable, nev), stats (nullable; cg_* count GMRES iterations and
- * solves, lanczos_steps Arnoldi steps, bytes_alg 896 n B per apply).
+ * solves, lanczos_steps Arnoldi steps, bytes_alg (320 + the medium's bytes
+ * per voxel of nsf_plan_medium_info) n B per apply).
  * Allocates and frees its bases ((m + 1) + (restart + 1) + 3 vectors of 4n
  * complex values).  Returns NSF_OK, NSF_NOT_CONVERGED (results filled) or an
  * error.  Synchronises.

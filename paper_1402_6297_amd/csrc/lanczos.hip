@@ -272,7 +272,7 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
     NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, p->d_cg + r->len, r->len, p->d_partial, p->d_state,
                               r->cg_rtol, 5000, s, m ? r->AV : nullptr, r->len, m, m ? p->d_coef : nullptr));
   }
-  bool graph = cgg != nullptr;
+  bool graph = cgg != nullptr && !debug_sync();
   for (Run* r : act) graph = graph && r->p->opt_cg_graph;
   hipStream_t ws = s;
   if (graph) {
@@ -912,7 +912,9 @@ int nsf_eigs(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
   NSF_HIP(p, hipStreamSynchronize(p->stream));
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   finish_run(r, omega_host, resid_host, stats, ms);
-  return r.converged ? NSF_OK : NSF_NOT_CONVERGED;
+  const int status = r.converged ? NSF_OK : NSF_NOT_CONVERGED;
+  trace_solve("nsf_eigs", p, 0, nev, status, r.st, r.eta.data());
+  return status;
 }
 
 int nsf_batch_create(nsf_batch* out, int count, const int* grids, const double* ks, double a, double alpha,
@@ -1032,6 +1034,7 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
       finish_run(r, omega_host + (size_t)i * nev, resid_host ? resid_host + (size_t)i * nev : nullptr,
                  stats ? stats + i : nullptr, ms);
       if (!r.converged) worst = NSF_NOT_CONVERGED;
+      trace_solve("nsf_batch_eigs", r.p, i, nev, r.converged ? NSF_OK : NSF_NOT_CONVERGED, r.st, r.eta.data());
     }
     // free this wave's Lanczos storage before the next wave
     if (w1 < B)

@@ -723,22 +723,22 @@ int nsf_eigs_nfsep(nsf_plan p, int nev, double res_tol, double inner_rtol, int m
     if (resid_host) resid_host[i] = best.eta[i];
     if (best.eta[i] <= res_tol) ++nconv;
   }
-  if (stats) {
-    *stats = nsf_stats{};
-    stats->matvecs = cnt.matvecs;
-    stats->cg_iters_total = cnt.iters;
-    stats->cg_solves = cnt.solves;
-    stats->lanczos_steps = steps;
-    stats->restarts = restarts;
-    stats->converged = nconv;
-    stats->ortho_passes = cnt.passes;
-    stats->cg_iters_avg = cnt.solves ? (double)cnt.iters / cnt.solves : 0.0;
-    stats->bytes_alg = (double)kNfsepApplyBytesPerVoxel * (double)n * (double)cnt.matvecs;
-    stats->ms_cg = t_gmres;
-    stats->ms_orth = t_orth;
-    stats->ms_restart = t_rest;
-    stats->ms_total = ms_since(t_start);
-  }
+  nsf_stats st{};
+  st.matvecs = cnt.matvecs;
+  st.cg_iters_total = cnt.iters;
+  st.cg_solves = cnt.solves;
+  st.lanczos_steps = steps;
+  st.restarts = restarts;
+  st.converged = nconv;
+  st.ortho_passes = cnt.passes;
+  st.cg_iters_avg = cnt.solves ? (double)cnt.iters / cnt.solves : 0.0;
+  st.bytes_alg = (double)(kNfsepFieldBytesPerVoxel + medium_voxel_bytes(p)) * (double)n * (double)cnt.matvecs;
+  st.ms_cg = t_gmres;
+  st.ms_orth = t_orth;
+  st.ms_restart = t_rest;
+  st.ms_total = ms_since(t_start);
+  if (stats) *stats = st;
+  trace_solve("nsf_eigs_nfsep", p, 0, nev, status, st, best.eta.data());
   return status;
 }
 

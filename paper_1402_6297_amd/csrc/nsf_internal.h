@@ -67,10 +67,11 @@ constexpr int kGenEntries = 21;
 // Entries of the NFSEP per-voxel factor i J B^{-1}: a full 6 x 6 matrix, row-major.
 constexpr int kFullEntries = 36;
 
-// Algorithmic HBM bytes per voxel of one apply with the NFSEP factor: read the
-// 4n input (64), write and read six fields (96 + 96), read 36 complex entries
-// (576), write the 4n output (64).
-constexpr int kNfsepApplyBytesPerVoxel = 896;
+// Algorithmic HBM bytes per voxel of one apply besides the medium: read the 4n
+// input (64), write and read six fields (96 + 96), write the 4n output (64).
+// The medium adds medium_voxel_bytes (576 for NFSEP factors per voxel, 2 with
+// a palette).
+constexpr int kNfsepFieldBytesPerVoxel = 320;
 
 // Largest palette of distinct per-voxel factors (general and NFSEP media); a
 // medium with more distinct voxels keeps its factors per voxel.
@@ -397,6 +398,16 @@ namespace nsf {
 int ensure_device(nsf_plan p);
 int set_error(nsf_plan p, int code, const std::string& msg);
 int hip_check(nsf_plan p, hipError_t e, const char* what);
+// NSF_SYNC_CHECK set (not "0"): every checked HIP call is followed by a device
+// synchronisation and its error check (debugging; graph capture is then off).
+bool debug_sync();
+// Medium bytes per voxel an apply reads (nsf_plan_medium_info's voxel_bytes).
+long long medium_voxel_bytes(nsf_plan p);
+// NSF_TRACE set: one JSON line per finished eigensolve (per instance of a
+// batch) with the counters and phase times, to stderr ("1" or "stderr") or
+// appended to the named file.
+void trace_solve(const char* call, nsf_plan p, int instance, int nev, int status, const nsf_stats& st,
+                 const double* resid);
 MediumView medium_view(nsf_plan p);
 int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip);
 // Pass dispatch (fast path when the axis allows it, else generic).

@@ -2,6 +2,7 @@
 #include <chrono>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -45,11 +46,54 @@ int set_error(nsf_plan p, int code, const std::string& msg) {
   return code;
 }
 
+bool debug_sync() {
+  const char* e = std::getenv("NSF_SYNC_CHECK");
+  return e && *e && *e != '0';
+}
+
 int hip_check(nsf_plan p, hipError_t e, const char* what) {
+  std::string suffix;
+  if (e == hipSuccess && debug_sync()) {  // NSF_SYNC_CHECK: surface errors of asynchronous work here
+    e = hipDeviceSynchronize();
+    suffix = " (device synchronisation after the call)";
+  }
   if (e == hipSuccess) return NSF_OK;
-  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e) + suffix;
   const int code = (e == hipErrorOutOfMemory) ? NSF_E_NOMEM : NSF_E_HIP;
   return set_error(p, code, msg);
+}
+
+long long medium_voxel_bytes(nsf_plan p) {
+  const int k = p->medium_kind;
+  const int entries = k == kMedGeneral ? kGenEntries : k == kMedNfsep ? kFullEntries : 0;
+  if (k == kMedNone) return 0;
+  if (!entries) return (long long)sizeof(double2);  // (eps, gamma) per voxel
+  if (p->palette > 0) return (long long)sizeof(unsigned short);
+  return (long long)sizeof(double2) * entries;
+}
+
+void trace_solve(const char* call, nsf_plan p, int instance, int nev, int status, const nsf_stats& st,
+                 const double* resid) {
+  const char* dest = std::getenv("NSF_TRACE");
+  if (!dest || !*dest || !std::strcmp(dest, "0")) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  FILE* f = (!std::strcmp(dest, "1") || !std::strcmp(dest, "stderr")) ? stderr : std::fopen(dest, "a");
+  if (!f) return;
+  double rmax = 0;
+  for (int i = 0; resid && i < nev; ++i) rmax = std::max(rmax, resid[i]);
+  const Geom& g = p->geom;
+  std::fprintf(f,
+               "{\"call\": \"%s\", \"instance\": %d, \"grid\": [%d, %d, %d], \"medium_kind\": %d, "
+               "\"nev\": %d, \"status\": %d, \"converged\": %d, \"max_residual\": %.6e, "
+               "\"matvecs\": %lld, \"inner_iters_total\": %lld, \"inner_solves\": %d, "
+               "\"inner_iters_avg\": %.3f, \"steps\": %d, \"restarts\": %d, \"ortho_passes\": %d, "
+               "\"ms_total\": %.3f, \"ms_inner\": %.3f, \"ms_orth\": %.3f, \"ms_restart\": %.3f, "
+               "\"bytes_alg\": %.6e}\n",
+               call, instance, g.n1, g.n2, g.n3, p->medium_kind, nev, status, st.converged, rmax, st.matvecs,
+               st.cg_iters_total, st.cg_solves, st.cg_iters_avg, st.lanczos_steps, st.restarts, st.ortho_passes,
+               st.ms_total, st.ms_cg, st.ms_orth, st.ms_restart, st.bytes_alg);
+  if (f != stderr) std::fclose(f);
 }
 
 int ensure_device(nsf_plan p) {
@@ -416,12 +460,7 @@ int nsf_plan_medium_info(nsf_plan p, int* palette, long long* voxel_bytes) {
   const int k = p->medium_kind;
   const int entries = k == kMedGeneral ? kGenEntries : k == kMedNfsep ? kFullEntries : 0;
   if (palette) *palette = entries ? p->palette : 0;
-  if (voxel_bytes) {
-    if (k == kMedNone) *voxel_bytes = 0;
-    else if (!entries) *voxel_bytes = (long long)sizeof(double2);  // (eps, gamma) per voxel
-    else if (p->palette > 0) *voxel_bytes = (long long)sizeof(unsigned short);
-    else *voxel_bytes = (long long)sizeof(double2) * entries;
-  }
+  if (voxel_bytes) *voxel_bytes = medium_voxel_bytes(p);
   return NSF_OK;
 }
 

@@ -9,6 +9,9 @@
 // candidate computes the same transforms; only the arithmetic order of the CG
 // reductions (partials per workgroup) can change, so results agree to rounding.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "nsf_internal.h"
@@ -50,6 +53,39 @@ int time_apply(nsf_plan p, const double2* u, double2* out, int reps, hipEvent_t 
   return NSF_OK;
 }
 
+// NSF_TUNE_CACHE lines: "nsf-tune n1 n2 n3 kind path mid xr yz pairs us_best us_default".
+bool cache_lookup(const Geom& g, int kind, Tiling* t, double* us_best, double* us_dflt) {
+  const char* path = std::getenv("NSF_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char tag[16];
+  int n1, n2, n3, k;
+  Tiling c{};
+  double b, d;
+  bool hit = false;
+  while (std::fscanf(f, "%15s %d %d %d %d %d %d %d %d %d %lf %lf", tag, &n1, &n2, &n3, &k, &c.path, &c.mid,
+                     &c.xr, &c.yz, &c.pairs, &b, &d) == 12) {
+    if (std::strcmp(tag, "nsf-tune") || n1 != g.n1 || n2 != g.n2 || n3 != g.n3 || k != kind) continue;
+    *t = c;  // the last matching line wins
+    *us_best = b;
+    *us_dflt = d;
+    hit = true;
+  }
+  std::fclose(f);
+  return hit;
+}
+
+void cache_store(const Geom& g, int kind, const Tiling& t, double us_best, double us_dflt) {
+  const char* path = std::getenv("NSF_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "nsf-tune %d %d %d %d %d %d %d %d %d %.3f %.3f\n", g.n1, g.n2, g.n3, kind, t.path, t.mid, t.xr,
+               t.yz, t.pairs, us_best, us_dflt);
+  std::fclose(f);
+}
+
 }  // namespace
 }  // namespace nsf
 
@@ -66,6 +102,24 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
   const Geom& g = p->geom;
   const long long len = 4 * g.n;
   const Tiling dflt{0, 16, 4, 16, 1};
+  {
+    Tiling c{};
+    double b = 0, d = 0;
+    if (cache_lookup(g, p->medium_kind, &c, &b, &d)) {
+      apply_tiling(p, c);
+      if (result) {
+        result->fft_path = c.path;
+        result->mid_cols = c.mid;
+        result->x_rows = c.xr;
+        result->yz_cols = c.yz;
+        result->mid_pairs = c.pairs;
+        result->us_best = b;
+        result->us_default = d;
+        result->tried = 0;
+      }
+      return NSF_OK;
+    }
+  }
   const bool fast = fast_axis(g.n1) || fast_axis(g.n2) || fast_axis(g.n3);
   const bool wave = wave_axis(g.n1) || wave_mid_ok(g);
   const Tiling saved{p->opt_fft_path, p->opt_mid_cols, g.x_rows, g.yz_cols, g.mid_pairs};
@@ -151,6 +205,7 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
   const int tried = (int)seen.size();
   apply_tiling(p, best);
   cleanup();
+  cache_store(g, p->medium_kind, best, best_ms * 1e3, dflt_ms * 1e3);
   if (result) {
     result->fft_path = best.path;
     result->mid_cols = best.mid;

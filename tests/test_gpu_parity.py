@@ -827,3 +827,45 @@ def test_eigs_rejects_bad_arguments():
             with pytest.raises(nsf.NsfError) as e:
                 P.eigs(nev, **bad)
             assert e.value.status == nsf.NSF_E_ARG
+
+
+# ------------------------------------------------------------ environment switches
+
+def test_trace_sync_check_and_tune_cache(tmp_path, monkeypatch):
+    """NSF_TRACE writes one JSON line per solve with the returned counters;
+    NSF_SYNC_CHECK (eager CG launches, a device synchronisation after every call)
+    reproduces the graph-replayed solve bit for bit; NSF_TUNE_CACHE replays a stored
+    tiling without timing anything."""
+    grid, k = (16, 16, 16), (0.1, 0.2, 0.3)
+    eps, gam = media.sphere_chiral(16)
+    trace = tmp_path / "trace.jsonl"
+    monkeypatch.setenv("NSF_TRACE", str(trace))
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        st, om, res, stats = P.eigs(4, res_tol=1e-9, cg_rtol=1e-11, seed=5)
+        monkeypatch.setenv("NSF_SYNC_CHECK", "1")
+        st2, om2, res2, stats2 = P.eigs(4, res_tol=1e-9, cg_rtol=1e-11, seed=5)
+        monkeypatch.delenv("NSF_SYNC_CHECK")
+    assert st == st2 == nsf.NSF_OK
+    assert np.array_equal(om, om2) and stats["matvecs"] == stats2["matvecs"]
+    with nsf.Plan((4, 4, 4), k) as Q:
+        Q.set_nfsep(*media.random_nonhhpd(4, seed=1))
+        st3, om3, res3, stats3 = Q.eigs_nfsep(3, res_tol=1e-10, inner_rtol=1e-12)
+    lines = [json.loads(x) for x in trace.read_text().splitlines()]
+    assert [x["call"] for x in lines] == ["nsf_eigs", "nsf_eigs", "nsf_eigs_nfsep"]
+    assert lines[0]["matvecs"] == stats["matvecs"] and lines[0]["grid"] == [16, 16, 16]
+    assert lines[0]["status"] == 0 and abs(lines[0]["max_residual"] - res.max()) <= 1e-6 * res.max()
+    assert lines[2]["medium_kind"] == nsf.NSF_MEDIUM_NFSEP and lines[2]["matvecs"] == stats3["matvecs"]
+    monkeypatch.delenv("NSF_TRACE")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("NSF_TUNE_CACHE", str(cache))
+    with nsf.Plan((32, 32, 32), k) as P:
+        P.set_chiral(*media.sphere_chiral(32))
+        t1 = P.autotune(reps=2)
+    with nsf.Plan((32, 32, 32), k) as P:
+        P.set_chiral(*media.sphere_chiral(32))
+        t2 = P.autotune(reps=2)
+    assert t1["tried"] > 0 and t2["tried"] == 0
+    assert {kk: t1[kk] for kk in ("fft_path", "mid_cols", "x_rows", "yz_cols", "mid_pairs")} == \
+           {kk: t2[kk] for kk in ("fft_path", "mid_cols", "x_rows", "yz_cols", "mid_pairs")}
+    assert cache.read_text().startswith("nsf-tune 32 32 32")
