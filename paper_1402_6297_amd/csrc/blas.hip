@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kRedThreads) void k_multi_axpy(const double2* __res
                                                             double2* __restrict__ z,
                                                             long long len,
                                                             const double2* __restrict__ gate,
-                                                            double tau2) {
+                                                            double tau2, double wscale) {
   __shared__ double2 cs[512];
   for (int i = threadIdx.x; i < m; i += kRedThreads) cs[i] = c[i];
   __syncthreads();
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kRedThreads) void k_multi_axpy(const double2* __res
       acc = csub(acc, cmul(cs[i], V[i * ld + e]));
       if (V2) acz = csub(acz, cmul(cs[i], V2[i * ld + e]));
     }
-    w[e] = acc;
+    w[e] = cscale(acc, wscale);
     if (V2) z[e] = acz;
   }
 }
@@ -728,11 +728,11 @@ hipError_t launch_cg_image(const double2* b, const double2* r, const double2* AV
 
 hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
                              long long len, hipStream_t s, const double2* V2, double2* z,
-                             const double2* gate, double tau2) {
-  if (m <= 0) return hipSuccess;
-  if (m > 512) return hipErrorInvalidValue;
+                             const double2* gate, double tau2, double wscale) {
+  if (m <= 0 && wscale == 1.0) return hipSuccess;
+  if (m < 0 || m > 512) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_multi_axpy, dim3(ew_grid(len)), dim3(kRedThreads), 0, s, V, V2, ld, m, c, w, z, len,
-                     gate, tau2);
+                     gate, tau2, wscale);
   return hipGetLastError();
 }
 

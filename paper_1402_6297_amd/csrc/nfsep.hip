@@ -128,27 +128,38 @@ int upload_coef(nsf_plan p, const cd* c, int m) {
 constexpr double kReorthArnoldi = 0.5;
 constexpr double kReorthGmres = 0.01;
 
-// c = conj(V_i)^T w for i < m into cf (host), then w -= V c; a second pass
-// when the first leaves no more than reorth ||w||^2.  On return nrm2 =
-// ||w||^2 after the update.
+// Classical Gram-Schmidt of w against V[0..m) where w is stored as V[m] (the
+// next slot of the basis): one pass over V[0..m] gives c_i = V_i^* w (i < m)
+// and ||w||^2 together; ||w - V c||^2 = ||w||^2 - sum |c_i|^2 (V orthonormal)
+// is known on the host before the update, so w -= V c is launched with the
+// normalisation folded in (w becomes the next unit basis vector).  A second
+// pass when the first leaves no more than reorth of ||w||^2.  cf (host)
+// receives c summed over the passes, nrm2 ||w||^2 before the normalisation.
+// One host synchronisation per pass.
 int gram_schmidt(nsf_plan p, const double2* V, long long len, int m, double2* w, cd* cf, double* nrm2,
                  int* passes, double reorth = kReorthArnoldi) {
   hipStream_t s = p->stream;
+  if (w != V + (size_t)m * len) return set_error(p, NSF_E_ARG, "Gram-Schmidt: w must follow the basis");
   for (int i = 0; i < m; ++i) cf[i] = 0.0;
-  int rc = dot_async(p, w, w, len, 0);
-  if (rc) return rc;
   for (int pass = 0; pass < 2; ++pass) {
-    NSF_HIP(p, launch_multi_dot(V, len, m, w, len, p->d_partial, p->d_coef, s));
-    NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_coef, sizeof(double2) * m, hipMemcpyDeviceToHost, s));
-    NSF_HIP(p, launch_multi_axpy(V, len, m, p->d_coef, w, len, s));
-    if ((rc = dot_async(p, w, w, len, 1))) return rc;
-    if ((rc = sync(p))) return rc;
-    for (int i = 0; i < m; ++i) cf[i] += C(p->h_res[64 + i]);
+    NSF_HIP(p, launch_multi_dot(V, len, m + 1, w, len, p->d_partial, p->d_coef, s));
+    NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_coef, sizeof(double2) * (m + 1), hipMemcpyDeviceToHost, s));
+    int rc = sync(p);
+    if (rc) return rc;
+    const double before = p->h_res[64 + m].x;
+    double removed = 0;
+    for (int i = 0; i < m; ++i) {
+      const cd c = C(p->h_res[64 + i]);
+      cf[i] += c;
+      removed += std::norm(c);
+    }
     if (passes) *passes += 1;
-    const double before = p->h_res[0].x, after = p->h_res[1].x;
+    const double after = before - removed;
+    const bool done = after > reorth * before || pass == 1;
+    const double sc = (done && after > 0.0 && std::isfinite(after)) ? 1.0 / std::sqrt(after) : 1.0;
+    NSF_HIP(p, launch_multi_axpy(V, len, m, p->d_coef, w, len, s, nullptr, nullptr, nullptr, 0.0, sc));
     *nrm2 = after;
-    if (after > reorth * before) break;
-    p->h_res[0].x = after;  // the reference for a further pass
+    if (done) break;
   }
   return NSF_OK;
 }
@@ -227,8 +238,7 @@ int gmres(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int 
       g[j] = cs[j] * g[j];
       for (int i = 0; i <= j; ++i) H[(size_t)j * (R + 1) + i] = h[i];
       ++j;
-      const bool small = std::abs(g[j]) <= rtol * bnorm;
-      if (hn > 0.0 && !small) NSF_HIP(p, launch_scale_copy(w, w, 1.0 / hn, 0.0, len, s));
+      const bool small = std::abs(g[j]) <= rtol * bnorm;  // (w is already normalised)
       if (small || !(hn > 0.0)) break;
     }
     // x += V_j y with R y = g (upper triangular)
@@ -578,14 +588,12 @@ int nsf_eigs_nfsep(nsf_plan p, int nev, double res_tol, double inner_rtol, int m
         for (int i = 0; i <= j; ++i) hsz += std::norm(hcol[i]);
         if (!(hn > 1e-13 * std::sqrt(hsz))) {
           // invariant subspace: continue from a fresh direction orthogonal to V
+          // (two passes, each leaving a unit vector)
           NSF_HIP(p, launch_randn(w, len, seed + 7919ULL * (steps + 1), s));
           std::vector<cd> tmp(j + 1);
           if ((rc2 = gram_schmidt(p, V, len, j + 1, w, tmp.data(), &nrm2, &cnt.passes))) return rc2;
           if ((rc2 = gram_schmidt(p, V, len, j + 1, w, tmp.data(), &nrm2, &cnt.passes))) return rc2;
-          NSF_HIP(p, launch_scale_copy(w, w, 1.0 / std::sqrt(nrm2), 0.0, len, s));
           hn = 0.0;
-        } else {
-          NSF_HIP(p, launch_scale_copy(w, w, 1.0 / hn, 0.0, len, s));
         }
         for (int i = 0; i <= j; ++i) Hm[(size_t)j * (m + 1) + i] = hcol[i];
         Hm[(size_t)j * (m + 1) + j + 1] = hn;
