@@ -415,28 +415,18 @@ __global__ __launch_bounds__(kRedThreads) void k_multi_dot_final(const double2* 
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// w -= sum_i c_i V[i] and, when V2 is given, z -= sum_i c_i V2[i] (the same
-// coefficients), eight basis vectors per unrolled step.  With a gate (the
-// squared norm of w in gate->x), every workgroup returns without touching w or
-// z when max_i |c_i|^2 <= tau2 * gate->x: w is then orthogonal to the basis to
-// relative level sqrt(tau2) and the update would change it by no more.
+// w = wscale (w - sum_i c_i V[i]) and, when V2 is given, z -= sum_i c_i V2[i]
+// (the same coefficients), eight basis vectors per unrolled step.
 __global__ __launch_bounds__(kRedThreads) void k_multi_axpy(const double2* __restrict__ V,
                                                             const double2* __restrict__ V2,
                                                             long long ld, int m,
                                                             const double2* __restrict__ c,
                                                             double2* __restrict__ w,
                                                             double2* __restrict__ z,
-                                                            long long len,
-                                                            const double2* __restrict__ gate,
-                                                            double tau2, double wscale) {
+                                                            long long len, double wscale) {
   __shared__ double2 cs[512];
   for (int i = threadIdx.x; i < m; i += kRedThreads) cs[i] = c[i];
   __syncthreads();
-  if (gate) {
-    double cmax = 0.0;
-    for (int i = 0; i < m; ++i) cmax = fmax(cmax, cs[i].x * cs[i].x + cs[i].y * cs[i].y);
-    if (cmax <= tau2 * gate->x) return;  // uniform over the workgroup
-  }
   for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < len;
        e += (long long)gridDim.x * kRedThreads) {
     double2 acc = w[e];
@@ -727,12 +717,11 @@ hipError_t launch_cg_image(const double2* b, const double2* r, const double2* AV
 }
 
 hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
-                             long long len, hipStream_t s, const double2* V2, double2* z,
-                             const double2* gate, double tau2, double wscale) {
+                             long long len, hipStream_t s, const double2* V2, double2* z, double wscale) {
   if (m <= 0 && wscale == 1.0) return hipSuccess;
   if (m < 0 || m > 512) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_multi_axpy, dim3(ew_grid(len)), dim3(kRedThreads), 0, s, V, V2, ld, m, c, w, z, len,
-                     gate, tau2, wscale);
+                     wscale);
   return hipGetLastError();
 }
 

@@ -330,23 +330,21 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
   return NSF_OK;
 }
 
-// A_r-cosine between w and every basis vector below which a gated
-// Gram-Schmidt pass leaves (w, z) as they are: 1e-2 of the residual tolerance,
-// at most 1e-10.  After the projected CG start the new direction is already
+// A_r-cosine between w and a basis vector below which the sparse Gram-Schmidt
+// step leaves that component in w: 1e-2 of the residual tolerance, at most
+// 1e-10.  After the projected CG start the new direction is already
 // A_r-orthogonal to the basis to about the CG tolerance; a basis that is
 // orthogonal to level c only reaches residuals of about c, hence the margin.
 double ortho_skip_cos(const Run* r) { return std::min(1e-10, 1e-2 * r->res_tol); }
 
-// Gram-Schmidt pass of (w, z) against V[0..nb) in the A_r inner product.  With
-// gate_slot >= 0, d_res[gate_slot] holds ||w||_A^2 and the update is skipped on
-// the device when every coefficient is below ortho_skip_cos ||w||_A.
-int ortho_pass(Run* r, int gate_slot = -1) {
+// Full classical Gram-Schmidt pass of (w, z) against V[0..nb) in the A_r inner
+// product (c = (A_r V)^* w; w -= V c, z -= (A_r V) c); ||w||_A^2 after it into
+// h_res[1].
+int ortho_pass(Run* r) {
   nsf_plan p = r->p;
   hipStream_t s = p->stream;
-  const double c = ortho_skip_cos(r);
   NSF_HIP(p, launch_multi_dot(r->AV, r->len, r->nb, r->w, r->len, p->d_partial, p->d_coef, s));
-  NSF_HIP(p, launch_multi_axpy(r->V, r->len, r->nb, p->d_coef, r->w, r->len, s, r->AV, r->z,
-                               gate_slot >= 0 ? p->d_res + gate_slot : nullptr, c * c));
+  NSF_HIP(p, launch_multi_axpy(r->V, r->len, r->nb, p->d_coef, r->w, r->len, s, r->AV, r->z));
   r->st.ortho_passes += 1;
   return dot_async(p, r->w, r->z, r->len, 1);
 }

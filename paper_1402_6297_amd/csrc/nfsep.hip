@@ -157,7 +157,7 @@ int gram_schmidt(nsf_plan p, const double2* V, long long len, int m, double2* w,
     const double after = before - removed;
     const bool done = after > reorth * before || pass == 1;
     const double sc = (done && after > 0.0 && std::isfinite(after)) ? 1.0 / std::sqrt(after) : 1.0;
-    NSF_HIP(p, launch_multi_axpy(V, len, m, p->d_coef, w, len, s, nullptr, nullptr, nullptr, 0.0, sc));
+    NSF_HIP(p, launch_multi_axpy(V, len, m, p->d_coef, w, len, s, nullptr, nullptr, sc));
     *nrm2 = after;
     if (done) break;
   }

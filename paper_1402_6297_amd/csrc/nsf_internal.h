@@ -290,14 +290,11 @@ hipError_t launch_cg_image(const double2* b, const double2* r, const double2* AV
 // indices as doubles in .x, device; m <= 512).
 hipError_t launch_sparse_axpy2(const double2* V, const double2* V2, long long ld, int m, const double2* c,
                                double2* w, double2* z, long long len, hipStream_t s);
-// w -= sum_i c[i] V_i and, if V2 is given, z -= sum_i c[i] V2_i  (c on device, m <= 512).
-// With a gate (device, ||w||^2 in gate->x) nothing is written when
-// max_i |c[i]|^2 <= tau2 ||w||^2.
-// wscale multiplies the updated w (not z).
+// w = wscale (w - sum_i c[i] V_i) and, if V2 is given, z -= sum_i c[i] V2_i
+// (c on device, m <= 512).
 hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
                              long long len, hipStream_t s, const double2* V2 = nullptr,
-                             double2* z = nullptr, const double2* gate = nullptr, double tau2 = 0.0,
-                             double wscale = 1.0);
+                             double2* z = nullptr, double wscale = 1.0);
 // V[:, 0:k] = V[:, 0:m] S (S device, m x k column-major complex), in place.
 hipError_t launch_rotate(double2* V, long long ld, int m, int k, const double2* S, long long len,
                          hipStream_t s);
