@@ -291,6 +291,17 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
 #pragma unroll
   for (int k1 = 0; k1 < N1; ++k1) T[(n2 + N2 * k1) * P] = v[k1];
   __syncthreads();
+  // the medium at this thread's positions k1 + N1 k2, in flight during the
+  // second radix
+  double2 mv[D][N2];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int k1 = n2 + d * N2;
+    if (k1 < N1) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) mv[d][k2] = eg[(k1 + N1 * k2) * stride];
+    }
+  }
   double2 out[D][N2];
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -321,7 +332,7 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
         const int z = k1 + N1 * k2;
-        const double2 m = eg[z * stride];
+        const double2 m = mv[d][k2];
         const double eps = m.x, gm = coupled ? m.y : 0.0;
         const double sc = inv_n / (eps - gm * gm);
         const double2 other = Tq[z * P];
