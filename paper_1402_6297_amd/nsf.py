@@ -163,14 +163,29 @@ def _check(status, plan=None):
     return status
 
 
-def _dptr(t, dtype_name):
-    """Device pointer of a contiguous torch tensor of the given dtype."""
+def _dptr(t, dtype_name, need=None):
+    """Device pointer of a contiguous torch tensor of the given dtype holding at
+    least ``need`` elements (the library reads or writes that many)."""
     import torch
 
     want = {"c128": torch.complex128, "f64": torch.float64}[dtype_name]
     if not isinstance(t, torch.Tensor) or t.dtype != want or not t.is_cuda or not t.is_contiguous():
         raise TypeError(f"expected a contiguous {want} tensor on a HIP device")
+    if need is not None and t.numel() < need:
+        raise ValueError(f"tensor holds {t.numel()} elements, the call needs {need}")
     return C.c_void_p(t.data_ptr())
+
+
+def _plan_n(plan):
+    """Voxel count n of a plan (host query)."""
+    n = C.c_longlong()
+    _check(lib().nsf_plan_query(plan, C.byref(n), None, None, None), plan)
+    return n.value
+
+
+def _host_exact(a, count, what):
+    if a.size != count:
+        raise ValueError(f"{what}: {a.size} values, the plan's grid needs {count}")
 
 
 def _hptr(a, dtype=np.float64):
@@ -213,38 +228,50 @@ def nsf_plan_query(plan):
     return dict(n=n.value, medium_kind=kind.value, sigma_min=smin.value, sigma_max=smax.value)
 
 
-def _medium_ptrs(eps, gamma):
+def _medium_ptrs(plan, eps, gamma):
+    n = _plan_n(plan)
     try:
         import torch
         if isinstance(eps, torch.Tensor):
-            return (eps, gamma), _dptr(eps, "f64"), _dptr(gamma, "f64"), 1
+            for t, what in ((eps, "eps"), (gamma, "gamma")):
+                if isinstance(t, torch.Tensor) and t.numel() != n:
+                    raise ValueError(f"{what}: {t.numel()} values, the plan's grid needs {n}")
+            return (eps, gamma), _dptr(eps, "f64", n), _dptr(gamma, "f64", n), 1
     except ImportError:  # pragma: no cover
         pass
     e, pe = _hptr(np.ravel(eps))
     g, pg = _hptr(np.ravel(gamma))
+    _host_exact(e, n, "eps")
+    _host_exact(g, n, "gamma")
     return (e, g), pe, pg, 0
 
 
 def nsf_set_medium_chiral(plan, eps, gamma):
-    keep, pe, pg, on_dev = _medium_ptrs(eps, gamma)
+    keep, pe, pg, on_dev = _medium_ptrs(plan, eps, gamma)
     return _check(lib().nsf_set_medium_chiral(plan, pe, pg, on_dev), plan)
 
 
 def nsf_set_medium_pseudochiral(plan, axis_a, axis_b, eps, gamma):
-    keep, pe, pg, on_dev = _medium_ptrs(eps, gamma)
+    keep, pe, pg, on_dev = _medium_ptrs(plan, eps, gamma)
     return _check(lib().nsf_set_medium_pseudochiral(plan, int(axis_a), int(axis_b), pe, pg, on_dev), plan)
 
 
 def _set_tensors(name, plan, eps, mu, xi, zeta):
     fields = [eps, mu, xi, zeta]
+    n = _plan_n(plan)
     try:
         import torch
         if isinstance(eps, torch.Tensor):
-            ptrs = [_dptr(t, "c128") for t in fields]
+            for t, what in zip(fields, ("eps", "mu", "xi", "zeta")):
+                if isinstance(t, torch.Tensor) and t.numel() != 9 * n:
+                    raise ValueError(f"{what}: {t.numel()} values, the plan's grid needs 9 x {n}")
+            ptrs = [_dptr(t, "c128", 9 * n) for t in fields]
             return _check(getattr(lib(), name)(plan, *ptrs, 1), plan)
     except ImportError:  # pragma: no cover
         pass
     keep = [np.ascontiguousarray(np.reshape(f, (-1, 3, 3)), dtype=np.complex128) for f in fields]
+    for k, what in zip(keep, ("eps", "mu", "xi", "zeta")):
+        _host_exact(k, 9 * n, what)
     return _check(getattr(lib(), name)(plan, *[C.c_void_p(k.ctypes.data) for k in keep], 0), plan)
 
 
@@ -259,28 +286,30 @@ def nsf_set_medium_nfsep(plan, eps, mu, xi, zeta):
     return _set_tensors("nsf_set_medium_nfsep", plan, eps, mu, xi, zeta)
 
 
-def _apply(name, plan, src, dst):
-    return _check(getattr(lib(), name)(plan, _dptr(src, "c128"), _dptr(dst, "c128")), plan)
+def _apply(name, plan, src, dst, src_per_n=4, dst_per_n=4):
+    n = _plan_n(plan)
+    return _check(getattr(lib(), name)(plan, _dptr(src, "c128", src_per_n * n),
+                                       _dptr(dst, "c128", dst_per_n * n)), plan)
 
 
 def nsf_fields(plan, y4n, eh6n):
-    return _apply("nsf_fields", plan, y4n, eh6n)
+    return _apply("nsf_fields", plan, y4n, eh6n, 4, 6)
 
 
 def nsf_apply_Pr(plan, y2n, x3n):
-    return _apply("nsf_apply_Pr", plan, y2n, x3n)
+    return _apply("nsf_apply_Pr", plan, y2n, x3n, 2, 3)
 
 
 def nsf_apply_Qr(plan, y2n, x3n):
-    return _apply("nsf_apply_Qr", plan, y2n, x3n)
+    return _apply("nsf_apply_Qr", plan, y2n, x3n, 2, 3)
 
 
 def nsf_apply_PrH(plan, x3n, y2n):
-    return _apply("nsf_apply_PrH", plan, x3n, y2n)
+    return _apply("nsf_apply_PrH", plan, x3n, y2n, 3, 2)
 
 
 def nsf_apply_QrH(plan, x3n, y2n):
-    return _apply("nsf_apply_QrH", plan, x3n, y2n)
+    return _apply("nsf_apply_QrH", plan, x3n, y2n, 3, 2)
 
 
 def nsf_apply_Ar(plan, u4n, out4n):
@@ -296,15 +325,17 @@ def nsf_profile_Ar(plan, u4n, out4n, reps=20):
     ms = (C.c_double * 16)()
     npass = C.c_int()
     whole = C.c_double()
-    _check(lib().nsf_profile_Ar(plan, _dptr(u4n, "c128"), _dptr(out4n, "c128"), int(reps), ms, 16,
-                                C.byref(npass), C.byref(whole)), plan)
+    n = _plan_n(plan)
+    _check(lib().nsf_profile_Ar(plan, _dptr(u4n, "c128", 4 * n), _dptr(out4n, "c128", 4 * n), int(reps),
+                                ms, 16, C.byref(npass), C.byref(whole)), plan)
     return [ms[i] for i in range(npass.value)], whole.value
 
 
 def nsf_cg_solve(plan, b, x, rtol=1e-10, maxit=10000):
     it, rel = C.c_int(), C.c_double()
-    st = _check(lib().nsf_cg_solve(plan, _dptr(b, "c128"), _dptr(x, "c128"), float(rtol), int(maxit),
-                                   C.byref(it), C.byref(rel)), plan)
+    n = _plan_n(plan)
+    st = _check(lib().nsf_cg_solve(plan, _dptr(b, "c128", 4 * n), _dptr(x, "c128", 4 * n), float(rtol),
+                                   int(maxit), C.byref(it), C.byref(rel)), plan)
     return st, it.value, rel.value
 
 
@@ -320,8 +351,9 @@ def nsf_apply_nfsep(plan, y4n, out4n):
 
 def nsf_nfsep_solve(plan, b, x, rtol=1e-10, maxit=0, restart=0):
     it, rel = C.c_int(), C.c_double()
-    st = _check(lib().nsf_nfsep_solve(plan, _dptr(b, "c128"), _dptr(x, "c128"), float(rtol), int(maxit),
-                                      int(restart), C.byref(it), C.byref(rel)), plan)
+    n = _plan_n(plan)
+    st = _check(lib().nsf_nfsep_solve(plan, _dptr(b, "c128", 4 * n), _dptr(x, "c128", 4 * n), float(rtol),
+                                      int(maxit), int(restart), C.byref(it), C.byref(rel)), plan)
     return st, it.value, rel.value
 
 
@@ -330,7 +362,7 @@ def nsf_eigs_nfsep(plan, nev, res_tol=1e-8, inner_rtol=1e-10, max_basis=0, max_r
     omega = np.zeros(nev, dtype=np.complex128)
     resid = np.zeros(nev)
     st = nsf_stats()
-    yp = _dptr(Y, "c128") if Y is not None else None
+    yp = _dptr(Y, "c128", int(nev) * 4 * _plan_n(plan)) if Y is not None else None
     status = _check(lib().nsf_eigs_nfsep(plan, int(nev), float(res_tol), float(inner_rtol), int(max_basis),
                                          int(max_restarts), C.c_ulonglong(seed), C.c_void_p(omega.ctypes.data),
                                          yp, resid.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)), plan)
@@ -342,7 +374,7 @@ def nsf_eigs(plan, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, max_restarts=0
     omega = np.zeros(nev)
     resid = np.zeros(nev)
     st = nsf_stats()
-    yp = _dptr(Y, "c128") if Y is not None else None
+    yp = _dptr(Y, "c128", int(nev) * 4 * _plan_n(plan)) if Y is not None else None
     status = _check(lib().nsf_eigs(plan, int(nev), float(res_tol), float(cg_rtol), int(max_basis),
                                    int(max_restarts), C.c_ulonglong(seed),
                                    omega.ctypes.data_as(C.POINTER(C.c_double)), yp,
@@ -351,11 +383,14 @@ def nsf_eigs(plan, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, max_restarts=0
 
 
 def nsf_eig_grad(plan, omega, Y, weights, d_eps, d_gamma):
-    om, _ = _hptr(omega)
-    w, _ = _hptr(weights)
+    om, _ = _hptr(np.ravel(omega))
+    w, _ = _hptr(np.ravel(weights))
+    if w.size != om.size:
+        raise ValueError(f"{w.size} weights for {om.size} eigenvalues")
+    n = _plan_n(plan)
     return _check(lib().nsf_eig_grad(plan, len(om), om.ctypes.data_as(C.POINTER(C.c_double)),
-                                     _dptr(Y, "c128"), w.ctypes.data_as(C.POINTER(C.c_double)),
-                                     _dptr(d_eps, "f64"), _dptr(d_gamma, "f64")), plan)
+                                     _dptr(Y, "c128", om.size * 4 * n), w.ctypes.data_as(C.POINTER(C.c_double)),
+                                     _dptr(d_eps, "f64", n), _dptr(d_gamma, "f64", n)), plan)
 
 
 def nsf_hermitian_eig(H):
@@ -413,7 +448,10 @@ def nsf_batch_eigs(batch, count, nev, res_tol=1e-8, cg_rtol=1e-10, max_basis=0, 
     wave = C.c_int()
     yp = None
     if Y is not None:
-        yp = (C.c_void_p * count)(*[(_dptr(t, "c128").value if t is not None else None) for t in Y])
+        if len(Y) != count:
+            raise ValueError(f"{len(Y)} vector buffers for {count} instances")
+        yp = (C.c_void_p * count)(*[(_dptr(t, "c128", int(nev) * 4 * _plan_n(nsf_batch_plan(batch, i))).value
+                                     if t is not None else None) for i, t in enumerate(Y)])
     status = _check(lib().nsf_batch_eigs(batch, int(nev), float(res_tol), float(cg_rtol), int(max_basis),
                                          int(max_restarts), C.c_ulonglong(seed),
                                          omega.ctypes.data_as(C.POINTER(C.c_double)),
@@ -427,7 +465,8 @@ def nsf_eigs_set_start(plan, Y0):
     if Y0 is None:
         return _check(lib().nsf_eigs_set_start(plan, None, 0), plan)
     count = Y0.shape[0] if Y0.dim() == 2 else 1
-    return _check(lib().nsf_eigs_set_start(plan, _dptr(Y0, "c128"), int(count)), plan)
+    return _check(lib().nsf_eigs_set_start(plan, _dptr(Y0, "c128", count * 4 * _plan_n(plan)), int(count)),
+                  plan)
 
 
 def nsf_plan_autotune(plan, reps=10):

@@ -829,6 +829,57 @@ def test_eigs_rejects_bad_arguments():
             assert e.value.status == nsf.NSF_E_ARG
 
 
+def test_short_buffers_and_wrong_media_sizes_are_rejected():
+    """The binding checks every buffer against the plan's n before the library
+    is called, so a short tensor never reaches a kernel."""
+    grid, k = (8, 8, 8), (0.1, 0.2, 0.3)
+    n = 512
+    eps, gam = media.sphere_chiral(8)
+
+    def c(m):
+        return torch.zeros(m, dtype=torch.complex128, device="cuda")
+
+    with nsf.Plan(grid, k) as P:
+        with pytest.raises(ValueError):
+            P.set_chiral(eps.ravel()[:-1], gam)
+        with pytest.raises(ValueError):
+            P.set_chiral(dev(eps.ravel()[:-1]), dev(gam))
+        with pytest.raises(ValueError):
+            P.set_tensor(*[np.zeros((n - 1, 3, 3), np.complex128)] * 4)
+        P.set_chiral(eps, gam)
+        with pytest.raises(ValueError):
+            P.Ar(c(4 * n), c(4 * n - 1))
+        with pytest.raises(ValueError):
+            P.Br(c(4 * n - 1), c(4 * n))
+        with pytest.raises(ValueError):
+            P.Pr(c(2 * n), c(3 * n - 1))
+        with pytest.raises(ValueError):
+            P.QrH(c(3 * n - 1), c(2 * n))
+        with pytest.raises(ValueError):
+            P.fields(c(4 * n), c(6 * n - 1))
+        with pytest.raises(ValueError):
+            P.cg(c(4 * n), c(4 * n - 1))
+        with pytest.raises(ValueError):
+            P.eigs(3, Y=c(3 * 4 * n - 1))
+        with pytest.raises(ValueError):
+            P.set_start(c(4 * n - 1))
+        Y = c(2 * 4 * n)
+        st, om, res, _ = P.eigs(2, res_tol=1e-10, cg_rtol=1e-12, Y=Y)  # exact sizes pass
+        assert st == nsf.NSF_OK
+        de = torch.empty(n, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
+            P.eig_grad(om, Y, np.ones(2), de[: n - 1], de.clone())
+        with pytest.raises(ValueError):
+            P.eig_grad(om, Y, np.ones(3), de, de.clone())
+    with nsf.Batch([grid, grid], [k, k]) as B:
+        B.set_chiral(0, eps, gam)
+        B.set_chiral(1, eps, gam)
+        with pytest.raises(ValueError):
+            B.eigs(2, Y=[c(2 * 4 * n)])
+        with pytest.raises(ValueError):
+            B.eigs(2, Y=[None, c(2 * 4 * n - 1)])
+
+
 # ------------------------------------------------------------ environment switches
 
 def test_trace_sync_check_and_tune_cache(tmp_path, monkeypatch):
