@@ -451,8 +451,10 @@ int nsf_eig_grad(nsf_plan plan, int nev, const double* omega_host,
  * one schedule.  Instances with the same grid share every launch of the CG
  * iterations and A_r applies (the instance is a launch dimension, each with
  * its own convergence flag), and the host synchronises once per Lanczos
- * phase for the whole batch.  Results equal per-instance nsf_eigs calls up to
- * rounding and the start vectors (instance i uses seed + 1000003 i).
+ * phase for the whole batch.  An instance of 2^21 voxels or more (128^3)
+ * fills the GPU by itself and runs alone, exactly as nsf_eigs.  Results equal
+ * per-instance nsf_eigs calls up to rounding and the start vectors (instance
+ * i uses seed + 1000003 i).
  *
  * nsf_batch_create: count instances; grids is count x 3 (n1, n2, n3), ks is
  *   count x 3 Bloch vectors; a, alpha, beta as nsf_plan_create; all instances
@@ -464,8 +466,9 @@ int nsf_eig_grad(nsf_plan plan, int nev, const double* omega_host,
  *   are count x nev (row i for instance i), stats count entries (nullable),
  *   Y_dev (nullable) count device pointers (each nullable) that receive the
  *   instance's 4n x nev Ritz vectors as nsf_eigs's Y_dev.
- *   Instances run in waves sized to free device memory; *wave_size (nullable)
- *   receives the wave length.  Returns NSF_OK when every instance converged,
+ *   Instances below 2^21 voxels run in shared waves sized to free device
+ *   memory, larger ones one per wave; *wave_size (nullable) receives the
+ *   shared wave length (1 when no instance shares).  Returns NSF_OK when every instance converged,
  *   NSF_NOT_CONVERGED otherwise, or an error.  Synchronises.
  */
 typedef struct nsf_batch_s* nsf_batch;
