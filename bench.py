@@ -528,7 +528,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "independent k-points shard across GPUs without communication, see DESIGN.md",
+              "independent k-points and instances shard across GPUs without communication; one grid "
+              "split in z-slabs would need an all-to-all before and after the fused z pass",
               file=sys.stderr)
         sys.exit(2)
 
