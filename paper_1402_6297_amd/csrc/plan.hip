@@ -189,8 +189,6 @@ hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, co
 // A_r u in five passes: [synthesis + inverse x] [inverse y]
 // [inverse z, middle factor, forward z] [forward y] [forward x + projection].
 int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip) {
-  const Geom& g = p->geom;
-  hipStream_t s = p->stream;
   double2* F = p->d_fields;
   NSF_HIP(p, pass_x_inv(p, kPartBoth, u, F, skip));
   NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, skip));
@@ -835,7 +833,6 @@ int nsf_apply_Pr(nsf_plan p, const nsf_c128* y2n, nsf_c128* x3n) {
   if (!p || !y2n || !x3n) return set_error(p, NSF_E_ARG, "NULL argument");
   int rc = ensure_device(p);
   if (rc) return rc;
-  const Geom& g = p->geom;
   auto* x = reinterpret_cast<double2*>(x3n);
   NSF_HIP(p, pass_x_inv(p, kPartP, reinterpret_cast<const double2*>(y2n), x, nullptr));
   NSF_HIP(p, pass_yz(p, 1, +1, 3, x, 0, 0, nullptr));
@@ -847,7 +844,6 @@ int nsf_apply_Qr(nsf_plan p, const nsf_c128* y2n, nsf_c128* x3n) {
   if (!p || !y2n || !x3n) return set_error(p, NSF_E_ARG, "NULL argument");
   int rc = ensure_device(p);
   if (rc) return rc;
-  const Geom& g = p->geom;
   auto* x = reinterpret_cast<double2*>(x3n);
   NSF_HIP(p, pass_x_inv(p, kPartQ, reinterpret_cast<const double2*>(y2n), x, nullptr));
   NSF_HIP(p, pass_yz(p, 1, +1, 3, x, 0, 0, nullptr));
@@ -891,7 +887,6 @@ int nsf_profile_Ar(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n, int reps, d
   if (p->medium_kind == kMedNone) return set_error(p, NSF_E_STATE, "no medium set");
   int rc = ensure_device(p);
   if (rc) return rc;
-  const Geom& g = p->geom;
   hipStream_t s = p->stream;
   double2* F = p->d_fields;
   const double2* u = reinterpret_cast<const double2*>(u4n);

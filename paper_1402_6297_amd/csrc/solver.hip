@@ -185,11 +185,9 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
   const long long len = 4 * p->geom.n;
   double2* r = p->d_cg;
   double2* pp = r + len;
-  double2* q = pp + len;
   hipStream_t s = p->stream;
   CgState* st = p->d_state;
   const int nparts = reduce_parts_for(len);
-  const int* skip = &st->done;
   NSF_HIP(p, launch_cg_init(b, x, r, pp, len, p->d_partial, st, rtol, maxit, s));
   // Fused iterations when the x axis has a two-level pass: the CG updates
   // ride in the first and last FFT pass of every A_r apply.
