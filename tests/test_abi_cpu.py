@@ -44,6 +44,8 @@ def test_plan_create_valid_and_query():
     ((7, 16, 16, 1.0, (0.1, 0.2, 0.3)), nsf.NSF_E_ARG),            # prime factor 7
     ((1024, 2, 2, 1.0, (0.1, 0.2, 0.3)), nsf.NSF_E_ARG),           # too long an axis
     ((1, 16, 16, 1.0, (0.1, 0.2, 0.3)), nsf.NSF_E_ARG),
+    ((0, 16, 16, 1.0, (0.1, 0.2, 0.3)), nsf.NSF_E_ARG),            # empty grid
+    ((16, -4, 16, 1.0, (0.1, 0.2, 0.3)), nsf.NSF_E_ARG),
     ((16, 16, 16, -1.0, (0.1, 0.2, 0.3)), nsf.NSF_E_ARG),
     ((16, 16, 16, 1.0, (float("nan"), 0.2, 0.3)), nsf.NSF_E_ARG),
 ])
@@ -78,6 +80,27 @@ def test_medium_validation_on_host():
     with pytest.raises(nsf.NsfError) as e:
         nsf.nsf_set_medium_pseudochiral(p, 1, 1, eps, np.zeros(64))
     assert e.value.status == nsf.NSF_E_ARG
+    nsf.nsf_plan_destroy(p)
+
+
+def test_binding_rejects_wrong_medium_sizes_before_the_call():
+    """Host media must hold exactly n voxels (the C call reads n of each)."""
+    p = nsf.nsf_plan_create(4, 4, 4, 1.0, (0.1, 0.2, 0.3), stream=0)
+    eps, gam = np.full(64, 13.0), np.full(64, 0.5)
+    for bad in ((eps[:63], gam), (eps, np.zeros(65))):
+        with pytest.raises(ValueError):
+            nsf.nsf_set_medium_chiral(p, *bad)
+        with pytest.raises(ValueError):
+            nsf.nsf_set_medium_pseudochiral(p, 0, 1, *bad)
+    t = [np.zeros((63, 3, 3), np.complex128)] * 4
+    with pytest.raises(ValueError):
+        nsf.nsf_set_medium_tensor(p, *t)
+    with pytest.raises(ValueError):
+        nsf.nsf_set_medium_nfsep(p, *t)
+    try:  # the right sizes pass the binding and reach the library (which needs a device)
+        nsf.nsf_set_medium_chiral(p, eps, gam)
+    except nsf.NsfError as e:
+        assert e.status == nsf.NSF_E_HIP
     nsf.nsf_plan_destroy(p)
 
 
