@@ -60,6 +60,24 @@ def test_eigs_sphere128_as_benchmarked():
     check_pencil_pairs(om, res, Y, (0, nev - 1), grid, k, tens, 1e-8)
 
 
+def test_eigs_rods128_kpath_point_as_benchmarked():
+    """Pseudochiral x-y rods (eps 13, gamma 0.4, r 0.2) at 128^3, the 16th point of
+    the benchmarked Gamma-X-M-Gamma-R path (on X-M): nev 10, residual 1e-8, CG
+    1e-10, as in the benchmark's k-path leg."""
+    grid, nev = (128, 128, 128), 10
+    n = 128 ** 3
+    k = tuple(media.kpath_gxmgr(10)[15])
+    eps, gam = media.rods_pseudochiral(128)
+    tens = medium.tensors_pseudochiral(eps, gam, (0, 1))
+    with nsf.Plan(grid, k) as P:
+        P.set_pseudochiral(0, 1, eps, gam)
+        Y = torch.empty((nev, 4 * n), dtype=torch.complex128, device="cuda")
+        st, om, res, stats = P.eigs(nev, res_tol=1e-8, cg_rtol=1e-10, seed=0, Y=Y)
+    assert st == nsf.NSF_OK and res.max() <= 1e-8
+    assert np.all(om > 0) and np.all(np.diff(om) >= 0)
+    check_pencil_pairs(om, res, Y, (0, nev - 1), grid, k, tens, 1e-8)
+
+
 def test_eigs_nfsep_lossy64_as_benchmarked():
     """Lossy chiral sphere (eps 13 + 0.5i, gamma 0.5, r 0.3) at 64^3 outside the
     HHPD assumption, k = (0.1, 0.2, 0.3): 10 eigenvalues with positive real part
