@@ -30,7 +30,9 @@ def tensors_pseudochiral(eps, gamma, pair=(0, 1)):
     """Pseudochiral medium: xi = i gamma (e_a e_b^T + e_b e_a^T), zeta = xi^* (Sec. 4.3).
 
     The paper's example couples x and z, pair=(0, 2); the 128^3 rod workload
-    couples x and y, pair=(0, 1).
+    couples x and y, pair=(0, 1).  Pinned by the block matrices Sec. 4.3 prints,
+    its diagonal Phi (eps - gamma^2 on the coupled axes, eps on the third) and a
+    per-frequency GEP of the homogeneous medium (tests/test_oracle_pseudochiral.py).
     """
     eps = np.asarray(eps, dtype=np.float64).ravel()
     gamma = np.asarray(gamma, dtype=np.float64).ravel()
