@@ -124,7 +124,10 @@ enum {
                             pairs, keeps the best nev of the union, and stops
                             when nothing changed.  Needed for spectra with
                             multiple eigenvalues (symmetric media at symmetric
-                            k-points); not applied by nsf_batch_eigs           */
+                            k-points; air): without it a multiple eigenvalue
+                            may be returned fewer times than it occurs.
+                            nsf_batch_eigs applies each instance's setting
+                            after that instance has converged               */
   NSF_OPT_ORTHO_GATE = 9, /* eigensolver Gram-Schmidt: 1 removes from a new
                             Lanczos direction only its components whose
                             A_r-cosine with a basis vector exceeds 1e-2
@@ -136,12 +139,24 @@ enum {
                             nsf_eigs_nfsep, 4..500 (default 12: at 128^3 the
                             classical Gram-Schmidt over a long basis costs
                             more than the extra iterations of restarting)  */
-  NSF_OPT_MEDIUM_PALETTE = 11 /* general and NFSEP media, read by the next
+  NSF_OPT_MEDIUM_PALETTE = 11, /* general and NFSEP media, read by the next
                             nsf_set_medium_tensor / nsf_set_medium_nfsep: 1
                             stores the distinct voxel factors once plus a
                             16-bit index per voxel when there are at most
                             4096 of them (default; piecewise-constant media),
                             0 always stores one factor per voxel           */
+  NSF_OPT_CG_RELAX = 12  /* eigensolver inner CG tolerance (nsf_eigs,
+                            nsf_batch_eigs): 1 (default) starts at
+                            max(cg_rtol, 0.1 res_tol) and after each restart
+                            uses max(cg_rtol, min(0.3, 0.1 / eta) res_tol),
+                            eta the largest residual of the wanted Ritz pairs
+                            (relaxation of inexact Krylov methods: the later
+                            solves of a converging basis may be less
+                            accurate), back to cg_rtol for good once two
+                            restarts in a row fail to halve eta; 0 solves
+                            every system to cg_rtol.  The projected matrix is
+                            exact and the returned pairs are checked with
+                            exact applies either way                         */
 };
 
 /*
@@ -385,7 +400,9 @@ int nsf_cg_solve(nsf_plan plan, const nsf_c128* b, nsf_c128* x, double rtol,
  *   nev          1 <= nev <= 256
  *   res_tol      stop when every wanted pair has
  *                eta = ||B_r y - theta A_r y|| / (|theta| ||A_r y||) <= res_tol
- *   cg_rtol      relative tolerance of the inner CG solves
+ *   cg_rtol      relative tolerance of the inner CG solves (with
+ *                NSF_OPT_CG_RELAX on, the tightest one: later solves are
+ *                relaxed as the Ritz residuals fall)
  *   max_basis    Lanczos basis size m before a restart (0: 3*nev, at least
  *                nev + 8); m + 1 vectors of 4n are kept, plus A_r times them
  *   max_restarts 0: no limit other than 1000

@@ -13,7 +13,15 @@ An eigenvalue that belongs to a numerically degenerate cluster has no
 derivative of its own; only symmetric functions of the cluster do.  The
 backward pass therefore replaces the incoming weights dS/d omega_j by their
 mean over each cluster (a no-op when the weights are already equal there, as
-for a sum of eigenvalues), and warns when they were not.
+for a sum of eigenvalues), and warns when they were not.  That needs every
+copy of a multiple eigenvalue, so the forward pass runs the solver's
+multiplicity checks (fresh starts A_r-orthogonal to the converged pairs, until one changes nothing),
+and it solves for one pair more than it returns: when omega_nev and
+omega_{nev+1} form one cluster, a function of the first nev alone is not
+differentiable there, and the forward pass warns.
+
+No plan is held between the passes: the backward pass builds one for the saved
+medium, so the graph may be differentiated more than once (retain_graph=True).
 """
 from __future__ import annotations
 
@@ -34,6 +42,14 @@ def clusters(omega: np.ndarray, rtol: float) -> list[list[int]]:
         else:
             groups.append([j])
     return groups
+
+
+def cut_in_cluster(omega: np.ndarray, nev: int, rtol: float) -> bool:
+    """Whether omega[nev - 1] and omega[nev] (ascending) belong to one cluster."""
+    if len(omega) <= nev:
+        return False
+    a, b = omega[nev - 1], omega[nev]
+    return abs(b - a) <= rtol * max(abs(b), 1e-300)
 
 
 def cluster_weights(omega: np.ndarray, weights: np.ndarray, rtol: float) -> np.ndarray:
@@ -63,29 +79,34 @@ class NSFEig(torch.autograd.Function):
             raise TypeError("eps and gamma must be HIP device tensors")
         eps_c = eps.detach().contiguous()
         gam_c = gamma.detach().contiguous()
-        plan = nsf.Plan(grid, k)
-        plan.set_chiral(eps_c, gam_c)
-        n = plan.n
-        Y = torch.empty((nev, 4 * n), dtype=torch.complex128, device=eps.device)
-        st, om, res, stats = plan.eigs(nev, res_tol=res_tol, cg_rtol=cg_rtol, seed=seed, Y=Y)
+        with nsf.Plan(grid, k) as plan:
+            plan.set_chiral(eps_c, gam_c)
+            plan.set_option(nsf.NSF_OPT_VERIFY, 16)  # stops at the first check that changes nothing
+            n = plan.n
+            Y = torch.empty((nev + 1, 4 * n), dtype=torch.complex128, device=eps.device)
+            st, om, res, stats = plan.eigs(nev + 1, res_tol=res_tol, cg_rtol=cg_rtol, seed=seed, Y=Y)
         if st != nsf.NSF_OK:
             raise nsf.NsfError(st, f"eigensolve did not converge (residuals {res})")
-        ctx.plan = plan
-        ctx.omega = om
+        if cut_in_cluster(om, nev, cluster_rtol):
+            warnings.warn(f"omega_{nev} and omega_{nev + 1} are degenerate to rtol {cluster_rtol:g}: the "
+                          f"{nev} smallest eigenvalues are not differentiable functions of the medium there",
+                          RuntimeWarning, stacklevel=2)
+        ctx.grid, ctx.k = grid, k
+        ctx.omega = om[:nev]
         ctx.cluster_rtol = cluster_rtol
-        ctx.shape = eps.shape
-        ctx.save_for_backward(Y)
+        ctx.save_for_backward(eps_c, gam_c, Y[:nev])
         ctx.stats = stats
-        return torch.as_tensor(om, dtype=torch.float64, device=eps.device)
+        return torch.as_tensor(om[:nev], dtype=torch.float64, device=eps.device)
 
     @staticmethod
     def backward(ctx, grad_omega):
-        (Y,) = ctx.saved_tensors
+        eps_c, gam_c, Y = ctx.saved_tensors
         w = cluster_weights(ctx.omega, grad_omega.detach().double().cpu().numpy(), ctx.cluster_rtol)
-        d_eps = torch.empty(ctx.shape, dtype=torch.float64, device=Y.device)
+        d_eps = torch.empty(eps_c.shape, dtype=torch.float64, device=Y.device)
         d_gamma = torch.empty_like(d_eps)
-        ctx.plan.eig_grad(ctx.omega, Y, w, d_eps, d_gamma)
-        ctx.plan.close()
+        with nsf.Plan(ctx.grid, ctx.k) as plan:
+            plan.set_chiral(eps_c, gam_c)
+            plan.eig_grad(ctx.omega, Y, w, d_eps, d_gamma)
         return d_eps, d_gamma, None, None, None, None, None, None, None
 
 

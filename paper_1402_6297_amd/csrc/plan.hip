@@ -444,6 +444,10 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_ORTHO_GATE takes 0 or 1");
       p->opt_ortho_gate = value;
       return NSF_OK;
+    case NSF_OPT_CG_RELAX:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_RELAX takes 0 or 1");
+      p->opt_cg_relax = value;
+      return NSF_OK;
     case NSF_OPT_CG_GRAPH:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_GRAPH takes 0 or 1");
       p->opt_cg_graph = value;

@@ -22,3 +22,11 @@ def test_unequal_weights_in_a_cluster_are_averaged_with_a_warning():
     with pytest.warns(RuntimeWarning, match="degenerate"):
         w = autograd.cluster_weights(om, np.array([1.0, 0.0, 2.0]), 1e-8)
     assert np.allclose(w, [0.5, 0.5, 2.0])
+
+
+def test_cut_inside_a_cluster_is_detected():
+    om = np.array([1.0, 2.0, 2.0 * (1 + 1e-12), 3.0])
+    assert autograd.cut_in_cluster(om, 2, 1e-8)
+    assert not autograd.cut_in_cluster(om, 1, 1e-8)
+    assert not autograd.cut_in_cluster(om, 3, 1e-8)
+    assert not autograd.cut_in_cluster(om, 4, 1e-8)
