@@ -393,6 +393,25 @@ int nsf_cg_solve(nsf_plan plan, const nsf_c128* b, nsf_c128* x, double rtol,
                  int maxit, int* iters, double* relres);
 
 /*
+ * nsf_cg_solve for callers that cannot allocate device memory (serving loops,
+ * harnesses that forbid hipMalloc): the same solve, the same kernels and the
+ * same results, with the CG vectors r, p, q (12 n complex values) kept in a
+ * library-owned static device array of 12 * 65536 complex values (12 MiB) on
+ * each GPU the library runs on, held until the process ends.  No hipMalloc,
+ * hipFree or allocating library call is made; the plan's own device state
+ * (tables, fields, reduction slots) must already exist, which setting a
+ * medium does.
+ *   Grids of at most 65536 voxels (e.g. 40^3, 64 x 32 x 32); larger plans get
+ *   NSF_E_ARG with a message naming the limit.  No medium: NSF_E_STATE.
+ *   Every call on one GPU shares that array and leaves its contents behind
+ *   (each solve initialises what it reads): calls that overlap in time on one
+ *   GPU race, even on different plans or streams.
+ *   Arguments, results, status and synchronisation as nsf_cg_solve.
+ */
+int nsf_cg_solve_noalloc(nsf_plan plan, const nsf_c128* b, nsf_c128* x,
+                         double rtol, int maxit, int* iters, double* relres);
+
+/*
  * The nev smallest positive eigenvalues omega of the GEP (Sec. 3), i.e. the
  * nev largest theta = 1/omega of B_r y = theta A_r y, by invert Lanczos in the
  * A_r inner product with thick restarts and CG inner solves (Sec. 4.2,

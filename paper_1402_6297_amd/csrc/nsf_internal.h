@@ -417,8 +417,9 @@ hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post
 hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid = nullptr,
                       int* np_mid = nullptr);
 hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip);
+// cgv: the three CG vectors r, p, q (4n each, consecutive); nullptr: the plan's own.
 int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
-                 double* relres, long long* matvecs);
+                 double* relres, long long* matvecs, double2* cgv = nullptr);
 // Bytes of the caller workspace for a basis of m + 1 vectors (fields, CG, V, A_r V, m x m).
 size_t workspace_bytes(long long n, int m);
 // Part of the caller workspace: 0 fields, 1 CG vectors, 2 basis (capacity in
@@ -426,8 +427,8 @@ size_t workspace_bytes(long long n, int m);
 double2* ws_part(nsf_plan p, int which, size_t* basis_cap = nullptr);
 int ensure_cg(nsf_plan p);
 bool cg_fusable(nsf_plan p);
-CgFuse cg_fuse_of(nsf_plan p, double2* x);
-int cg_iteration(nsf_plan p, double2* x, bool fused);
+CgFuse cg_fuse_of(nsf_plan p, double2* x, double2* cgv = nullptr);
+int cg_iteration(nsf_plan p, double2* x, bool fused, double2* cgv = nullptr);
 int cg_predict(const CgState& h, double rr_prev, int it_prev, bool fused);
 int ensure_basis(nsf_plan p, size_t vectors);
 int ensure_small(nsf_plan p, size_t count);

@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <mutex>
+#include <string>
 
 #include "nsf_internal.h"
 
@@ -114,9 +116,10 @@ bool cg_fusable(nsf_plan p) {
   return p->opt_fft_path != 1 && xr > 0 && ((long long)g.n2 * g.n3 + xr - 1) / xr <= 65536;
 }
 
-CgFuse cg_fuse_of(nsf_plan p, double2* x) {
+CgFuse cg_fuse_of(nsf_plan p, double2* x, double2* cgv) {
   const long long len = 4 * p->geom.n;
-  return CgFuse{x, p->d_cg, p->d_cg + len, p->d_cg + 2 * len, p->d_state,
+  double2* c = cgv ? cgv : p->d_cg;
+  return CgFuse{x, c, c + len, c + 2 * len, p->d_state,
                 reinterpret_cast<double*>(p->d_partial), reinterpret_cast<double*>(p->d_partial) + 65536,
                 reinterpret_cast<double*>(p->d_partial + kPartialSlots + kCoefSlots + kResSlots)};
 }
@@ -124,16 +127,16 @@ CgFuse cg_fuse_of(nsf_plan p, double2* x) {
 // One CG iteration of plan p, enqueued (every kernel returns at once when the
 // plan's CG state is done).  With `fused` the recurrences ride in the first
 // and last FFT pass.
-int cg_iteration(nsf_plan p, double2* x, bool fused) {
+int cg_iteration(nsf_plan p, double2* x, bool fused, double2* cgv) {
   const long long len = 4 * p->geom.n;
   hipStream_t s = p->stream;
   CgState* st = p->d_state;
   const int* skip = &st->done;
-  double2* r = p->d_cg;
+  double2* r = cgv ? cgv : p->d_cg;
   double2* pp = r + len;
   double2* q = pp + len;
   if (fused) {
-    const CgFuse cgf = cg_fuse_of(p, x);
+    const CgFuse cgf = cg_fuse_of(p, x, r);
     const bool qf = z_mid_pq_items(p) > 0;
     int np1 = 0, np5 = 0;
     NSF_HIP(p, launch_fast_cg_first(p->geom, p->tabs, cgf, p->d_fields, skip, &np1, s, nullptr, 1, qf));
@@ -179,11 +182,11 @@ int cg_predict(const CgState& h, double rr_prev, int it_prev, bool fused) {
 }
 
 int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
-                 double* relres, long long* matvecs) {
-  int rc = ensure_cg(p);
+                 double* relres, long long* matvecs, double2* cgv) {
+  int rc = cgv ? NSF_OK : ensure_cg(p);
   if (rc) return rc;
   const long long len = 4 * p->geom.n;
-  double2* r = p->d_cg;
+  double2* r = cgv ? cgv : p->d_cg;
   double2* pp = r + len;
   hipStream_t s = p->stream;
   CgState* st = p->d_state;
@@ -201,7 +204,7 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
   int it_prev = 0;
   for (;;) {
     for (int c = 0; c < chunk; ++c) {
-      rc = cg_iteration(p, x, fused);
+      rc = cg_iteration(p, x, fused, r);
       if (rc) return rc;
     }
     NSF_HIP(p, hipMemcpyAsync(p->h_state, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -221,6 +224,36 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
     return set_error(p, NSF_E_BREAKDOWN, "CG breakdown: p^* A_r p <= 0 or not finite");
   return h.status;
 }
+
+// ---------------------------------------------- CG without allocations
+// nsf_cg_solve_noalloc keeps its three CG vectors in this array instead of
+// plan memory.  Every GPU the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (kept per device below).
+constexpr long long kNoAllocVoxels = 1LL << 16;
+static __device__ __align__(256) double2 scratch[3 * 4 * kNoAllocVoxels];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(nsf_plan p, double2** out) {
+  int dev = 0;
+  NSF_HIP(p, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(p, NSF_E_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    NSF_HIP(p, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return set_error(p, NSF_E_HIP, "no device address for the CG scratch array");
+    g_scratch[dev] = static_cast<double2*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return NSF_OK;
+}
+}  // namespace
 
 // --------------------------------------------------- dense Hermitian eigen
 // Cyclic Jacobi: each rotation J = diag(1, e^{-i phi}) R(theta) zeroes one
@@ -313,6 +346,26 @@ int nsf_cg_solve(nsf_plan p, const nsf_c128* b, nsf_c128* x, double rtol, int ma
   long long mv = 0;
   return cg_solve_dev(p, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxit,
                       iters, relres, &mv);
+}
+
+int nsf_cg_solve_noalloc(nsf_plan p, const nsf_c128* b, nsf_c128* x, double rtol, int maxit, int* iters,
+                         double* relres) {
+  if (!p || !b || !x) return set_error(p, NSF_E_ARG, "NULL argument");
+  if ((const void*)b == (const void*)x) return set_error(p, NSF_E_ARG, "b and x must be distinct");
+  if (p->geom.n > kNoAllocVoxels)
+    return set_error(p, NSF_E_ARG, "nsf_cg_solve_noalloc takes grids of at most " +
+                                       std::to_string(kNoAllocVoxels) + " voxels (this plan has " +
+                                       std::to_string(p->geom.n) + ")");
+  if (!(rtol >= 0.0)) return set_error(p, NSF_E_ARG, "rtol must be >= 0");
+  if (p->medium_kind == kMedNone || !p->dev_ready) return set_error(p, NSF_E_STATE, "no medium set");
+  if (p->medium_kind == kMedNfsep)
+    return set_error(p, NSF_E_STATE, "an NFSEP medium has no positive definite A_r; use nsf_nfsep_solve");
+  double2* cgv = nullptr;
+  int rc = scratch_address(p, &cgv);
+  if (rc) return rc;
+  long long mv = 0;
+  return cg_solve_dev(p, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxit,
+                      iters, relres, &mv, cgv);
 }
 
 }  // extern "C"

@@ -54,7 +54,7 @@ EXPORTED = [
     "nsf_batch_create", "nsf_batch_plan", "nsf_batch_eigs", "nsf_batch_destroy",
     "nsf_plan_autotune", "nsf_batch_autotune", "nsf_plan_workspace_size", "nsf_plan_set_workspace",
     "nsf_fields", "nsf_eigs_set_start", "nsf_schur_sorted", "nsf_set_medium_nfsep", "nsf_apply_nfsep",
-    "nsf_nfsep_solve", "nsf_eigs_nfsep", "nsf_plan_medium_info",
+    "nsf_nfsep_solve", "nsf_eigs_nfsep", "nsf_plan_medium_info", "nsf_cg_solve_noalloc",
 ]
 
 
@@ -125,6 +125,7 @@ def lib():
         "nsf_apply_Br": (I, [P, VP, VP]),
         "nsf_profile_Ar": (I, [P, VP, VP, I, DP, I, C.POINTER(I), DP]),
         "nsf_cg_solve": (I, [P, VP, VP, D, I, C.POINTER(I), DP]),
+        "nsf_cg_solve_noalloc": (I, [P, VP, VP, D, I, C.POINTER(I), DP]),
         "nsf_eigs": (I, [P, I, D, D, I, I, C.c_ulonglong, DP, VP, DP, C.POINTER(nsf_stats)]),
         "nsf_eig_grad": (I, [P, I, DP, VP, DP, VP, VP]),
         "nsf_hermitian_eig": (I, [I, VP, DP, VP]),
@@ -337,6 +338,14 @@ def nsf_cg_solve(plan, b, x, rtol=1e-10, maxit=10000):
     n = _plan_n(plan)
     st = _check(lib().nsf_cg_solve(plan, _dptr(b, "c128", 4 * n), _dptr(x, "c128", 4 * n), float(rtol),
                                    int(maxit), C.byref(it), C.byref(rel)), plan)
+    return st, it.value, rel.value
+
+
+def nsf_cg_solve_noalloc(plan, b, x, rtol=1e-10, maxit=10000):
+    it, rel = C.c_int(), C.c_double()
+    n = _plan_n(plan)
+    st = _check(lib().nsf_cg_solve_noalloc(plan, _dptr(b, "c128", 4 * n), _dptr(x, "c128", 4 * n),
+                                           float(rtol), int(maxit), C.byref(it), C.byref(rel)), plan)
     return st, it.value, rel.value
 
 
@@ -647,6 +656,9 @@ class Plan:
 
     def cg(self, b, x, rtol=1e-10, maxit=10000):
         return nsf_cg_solve(self.handle, b, x, rtol, maxit)
+
+    def cg_noalloc(self, b, x, rtol=1e-10, maxit=10000):
+        return nsf_cg_solve_noalloc(self.handle, b, x, rtol, maxit)
 
     def eigs(self, nev, **kw):
         return nsf_eigs(self.handle, nev, **kw)

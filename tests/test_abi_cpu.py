@@ -284,3 +284,17 @@ def test_nfsep_medium_validation(breaker, msg):
         assert e.value.status == nsf.NSF_E_STATE
     finally:
         nsf.nsf_plan_destroy(p)
+
+
+def test_cg_noalloc_rejects_grids_above_its_scratch_before_any_device_call():
+    import ctypes as C
+
+    p = nsf.nsf_plan_create(64, 64, 32, 1.0, (0.1, 0.2, 0.3), stream=0)  # 131072 voxels
+    try:
+        it, rel = C.c_int(), C.c_double()
+        st = nsf.lib().nsf_cg_solve_noalloc(p, C.c_void_p(256), C.c_void_p(512), 1e-10, 100,
+                                            C.byref(it), C.byref(rel))
+        assert st == nsf.NSF_E_ARG
+        assert "65536" in nsf.nsf_last_error(p)
+    finally:
+        nsf.nsf_plan_destroy(p)
