@@ -10,6 +10,13 @@ times (HIP events on the plan's stream) and the CPU oracle timed on the host
 are reported beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere128|rods128|sphere64]
+
+After the timed steps the default run adds, outside the timed region: the other
+configurations (128^3 rods apply, 64^3 and 16^3 eigensolves), the batched-vs-plain
+legs (the 40-point Gamma-X-M-Gamma-R path of the 128^3 rods, the 32-instance uneven
+batch), the gradient with central differences at 50 voxels (64^3), the paper's
+band-structure path G-X-M-R-G at 128^3 for both of its media, the chirality
+sweep (64^3), the NFSEP path (64^3) and the CPU oracle.
 """
 from __future__ import annotations
 
@@ -27,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SVD-FFT matvec GB/s at 128^3; eigenpairs/s batched vs plain at res≤1e-8"
 HBM_PEAK_GBPS = 8000.0
+MAX_RESTARTS = 100  # per eigensolve in the secondary legs (a converging 128^3 solve needs about 10)
 BYTES_PER_APPLY_PER_N = 336  # y in (64n) + 6 fields out (96n) + in (96n) + medium (16n) + out (64n)
 NFSEP_FIELD_BYTES_PER_N = 320  # the same field traffic; the NFSEP medium adds 576 B (per voxel) or 2 B (palette)
 
@@ -80,7 +88,7 @@ def batch_leg(name, log=sys.stderr):
     from paper_1402_6297_amd import nsf
 
     grids, ks, med, nev = batch_instances(name)
-    kw = dict(res_tol=1e-8, cg_rtol=1e-10, seed=0)
+    kw = dict(res_tol=1e-8, cg_rtol=1e-10, seed=0, max_restarts=MAX_RESTARTS)
     # plain: one plan at a time; plan set-up (tables, medium upload) is outside
     # the timed region in both schedules, only the eigensolves are timed
     t_plain = 0.0
@@ -94,11 +102,14 @@ def batch_leg(name, log=sys.stderr):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st, om, res, stats = P.eigs(nev, seed=kw["seed"] + 1000003 * i, res_tol=kw["res_tol"],
-                                        cg_rtol=kw["cg_rtol"])
+                                        cg_rtol=kw["cg_rtol"], max_restarts=kw["max_restarts"])
             torch.cuda.synchronize()
-            t_plain += time.perf_counter() - t0
+            dt = time.perf_counter() - t0
+            t_plain += dt
             plain_pairs += stats["converged"]
             plain_mv += stats["matvecs"]
+        print(f"[bench] {name} plain {i}: {g[0]}^3 k={np.round(k, 4).tolist()} status {st}, "
+              f"{stats['lanczos_steps']} steps, {dt:.2f} s", file=log, flush=True)
     print(f"[bench] {name} plain: {len(grids)} instances, {t_plain:.1f} s", file=log, flush=True)
     with nsf.Batch(grids, ks) as B:
         for i, m in enumerate(med):
@@ -196,16 +207,83 @@ def gamma_sweep_leg(n1=64, log=sys.stderr, nev=10):
             eps, gam = media.spheres_cylinders_chiral(n1, eps_in=eps_i, eps_out=1.0, gamma=gmm)
             with nsf.Plan((n1, n1, n1), (0.5, 0.0, 0.0)) as P:
                 P.set_chiral(eps, gam)
+                P.set_option(nsf.NSF_OPT_VERIFY, 16)  # k on a lattice axis of a cubic structure
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                st, om, res, stats = P.eigs(nev, res_tol=1e-8, cg_rtol=1e-10)
+                st, om, res, stats = P.eigs(nev, res_tol=1e-8, cg_rtol=1e-10, max_restarts=MAX_RESTARTS)
                 torch.cuda.synchronize()
                 out.append({"eps_i": eps_i, "gamma": gmm, "status": st, "s": round(time.perf_counter() - t0, 3),
                             "cg_iters_avg": round(stats["cg_iters_avg"], 2), "lanczos_steps": stats["lanczos_steps"],
                             "omega": [round(x, 8) for x in om.tolist()], "max_residual": float(res.max())})
             print(f"[bench] gamma sweep eps_i {eps_i} gamma {gmm}: cg avg {out[-1]['cg_iters_avg']}",
                   file=log, flush=True)
-    return {"workload": f"spheres+cylinders {n1}^3, k=(0.5,0,0), nev={nev}", "points": out}
+    return {"workload": f"spheres+cylinders {n1}^3, k=(0.5,0,0), nev={nev}, multiplicity check on",
+            "paper_pcg_iters_avg_128": {"eps_i=13, gamma 0.25->3": "39->90", "eps_i=1, gamma 0.05->0.9": "9->59",
+                                        "note": "MATLAB pcg to 1e-14 at 128^3 (context)"},
+            "points": out}
+
+
+# The paper's band-structure runs (Sec. 5, first test set): 128^3, spheres joined
+# by cylinders, G-X-M-R-G with ten wave vectors per segment, 10 smallest positive
+# omega; Lanczos iterations and CPU hours per k-point as printed there (MATLAB
+# eigs + pcg on 2x Intel Xeon X5687, 8 cores, 3.6 GHz).  Context, not targets.
+PAPER_BAND = (
+    ((13.0, 1.0, 0.5), {"lanczos_iters": "120-190", "lanczos_iters_avg": 143, "hours_per_k": "2.75-4",
+                        "hours_per_k_avg": 3.2}),
+    ((1.0, 1.0, 0.8), {"lanczos_iters": "100-200", "lanczos_iters_avg": 136, "hours_per_k": "2.1-4.1",
+                       "hours_per_k_avg": 2.8}),
+)
+
+
+def band_leg(per_seg, n1=128, log=sys.stderr, nev=10):
+    """The paper's band-structure workload on the GPU: both media along G-X-M-R-G
+    (per_seg wave vectors per segment, segment midpoints), each k-point one plain
+    eigensolve with the multiplicity check on (the path's symmetric k-points can
+    carry multiple eigenvalues).  Per-k Lanczos steps, CG iterations and seconds,
+    beside the paper's ranges."""
+    import torch
+
+    from paper_1402_6297_amd import media, nsf
+
+    ks = media.kpath_gxmrg(per_seg)
+    grid = (n1, n1, n1)
+    out = []
+    for (ei, eo, g), paper in PAPER_BAND:
+        eps, gam = media.spheres_cylinders_chiral(n1, eps_in=ei, eps_out=eo, gamma=g)
+        eps_d, gam_d = torch.from_numpy(eps).to("cuda"), torch.from_numpy(gam).to("cuda")
+        pts = []
+        for k in ks:
+            with nsf.Plan(grid, tuple(k)) as P:
+                P.set_chiral(eps_d, gam_d)
+                P.set_option(nsf.NSF_OPT_VERIFY, 16)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, om, res, stats = P.eigs(nev, res_tol=1e-8, cg_rtol=1e-10, max_restarts=MAX_RESTARTS)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            print(f"[bench] band ({ei:g},{eo:g},{g:g}) k={np.round(k, 4).tolist()}: status {st}, "
+                  f"{stats['lanczos_steps']} steps, {dt:.2f} s", file=log, flush=True)
+            pts.append({"k": [round(x, 6) for x in k.tolist()], "status": st, "s": round(dt, 3),
+                        "lanczos_steps": stats["lanczos_steps"], "cg_iters_avg": round(stats["cg_iters_avg"], 2),
+                        "applies": stats["matvecs"], "max_residual": float(res.max()),
+                        "omega_over_2pi": [round(x / (2 * np.pi), 8) for x in om.tolist()]})
+        steps = np.array([p["lanczos_steps"] for p in pts])
+        secs = np.array([p["s"] for p in pts])
+        summ = {"medium": f"(eps_i, eps_o, gamma) = ({ei:g}, {eo:g}, {g:g})", "k_points": len(pts),
+                "status_all_ok": all(p["status"] == 0 for p in pts),
+                "lanczos_steps_min_max_avg": [int(steps.min()), int(steps.max()), round(float(steps.mean()), 1)],
+                "cg_iters_avg": round(float(np.mean([p["cg_iters_avg"] for p in pts])), 2),
+                "s_per_k_min_max_avg": [round(float(secs.min()), 3), round(float(secs.max()), 3),
+                                        round(float(secs.mean()), 3)],
+                "max_residual": max(p["max_residual"] for p in pts),
+                "paper_matlab_2x_xeon_x5687": paper, "points": pts}
+        out.append(summ)
+        print(f"[bench] band {summ['medium']}: {len(pts)} k, Lanczos steps {summ['lanczos_steps_min_max_avg']}, "
+              f"{summ['s_per_k_min_max_avg'][2]} s per k", file=log, flush=True)
+        del eps_d, gam_d
+    return {"workload": f"spheres r=0.345 joined by cylinders s=0.11 (simple cubic), {n1}^3, G-X-M-R-G with "
+                        f"{per_seg} k per segment, nev={nev}, residual <= 1e-8, multiplicity check on",
+            "media": out}
 
 
 def nfsep_leg(n1=64, log=sys.stderr, nev=10):
@@ -338,7 +416,7 @@ def grad_leg(nvox, log=sys.stderr, h=1e-6, nev=4):
     grid, k = (64, 64, 64), (0.1, 0.1, 0.1)
     eps, gam = media.noise_chiral(64, sigma_vox=2.0, seed=0)
     n = eps.size
-    kw = dict(res_tol=1e-11, cg_rtol=1e-12)
+    kw = dict(res_tol=1e-11, cg_rtol=1e-12, max_restarts=MAX_RESTARTS)
     vox = np.random.default_rng(1).choice(n, size=nvox, replace=False)
     with nsf.Plan(grid, k) as P:
         P.set_chiral(eps, gam)
@@ -394,14 +472,46 @@ def grad_leg(nvox, log=sys.stderr, h=1e-6, nev=4):
             "max_abs_grad_gamma": float(scale[1, 0]), "s_fd_batch": round(t_fd, 2)}
 
 
-def cpu_baseline(w, eps, gam, budget_s=20.0):
-    """The oracle's matrix-free A_r apply on the host, bounded to ~budget_s."""
+def _oracle_apply_worker(job):
+    """One host process of the CPU baseline: build the oracle's medium tensors for
+    the workload, then time `reps` matrix-free A_r applies (numpy, one thread)."""
+    if job is None:
+        return None  # pool warm-up: the workers start before the GPU is touched
+    grid, k, kind, reps = job
+    from oracle import medium, nfgep
+    from paper_1402_6297_amd import media
+
+    eps, gam = media.sphere_chiral(grid[0]) if kind == "chiral" else media.rods_pseudochiral(grid[0])
+    tens = (medium.tensors_chiral(eps, gam) if kind in ("chiral", "scsc")
+            else medium.tensors_pseudochiral(eps, gam, (0, 1)))
+    u = media.random_vector(4 * grid[0] * grid[1] * grid[2], 0)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nfgep.apply_Ar(u, grid, k, tens)
+    return reps, time.perf_counter() - t0
+
+
+def host_workers():
+    """Host processes for the all-cores baseline: the CPUs this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(w, eps, gam, pool=None, nproc=1, budget_s=12.0):
+    """The oracle's matrix-free A_r apply on the host, as it stands: one process
+    (bounded to ~budget_s), then one process per host core running the same
+    applies at once (whole-host throughput), plus the oracle eigensolve times
+    stored with the golden files (measured on the build host)."""
     from oracle import medium, nfgep
     from paper_1402_6297_amd import media
 
     grid, k = w["grid"], w["k"]
     n = grid[0] * grid[1] * grid[2]
-    tens = (medium.tensors_chiral(eps, gam) if w["kind"] == "chiral"
+    tens = (medium.tensors_chiral(eps, gam) if w["kind"] in ("chiral", "scsc")
             else medium.tensors_pseudochiral(eps, gam, (0, 1)))
     u = media.random_vector(4 * n, 0)
     reps, t0 = 0, time.perf_counter()
@@ -411,11 +521,51 @@ def cpu_baseline(w, eps, gam, budget_s=20.0):
         el = time.perf_counter() - t0
         if el > budget_s or reps >= 10:
             break
-    return dict(value=BYTES_PER_APPLY_PER_N * n * reps / el / 1e9, unit="GB/s", cores=1,
-                kind="oracle",
-                sample=f"{reps} oracle A_r applies (numpy FFT, one thread) on the same {grid[0]}^3 "
-                       f"workload, {el:.1f} s; {el / reps * 1e3:.0f} ms per apply",
-                host_cpu=platform.processor() or platform.machine())
+    del tens, u
+    one = BYTES_PER_APPLY_PER_N * n * reps / el / 1e9
+    out = dict(value=one, unit="GB/s", cores=1, kind="oracle",
+               sample=f"{reps} oracle A_r applies (numpy FFT, one thread) on the same {grid[0]}^3 "
+                      f"workload, {el:.1f} s; {el / reps * 1e3:.0f} ms per apply",
+               host_cpu=host_cpu_model())
+    if pool is not None and nproc > 1:
+        jobs = [(tuple(grid), tuple(k), w["kind"], 2)] * nproc
+        t0 = time.perf_counter()
+        res = list(pool.map(_oracle_apply_worker, jobs))
+        wall = time.perf_counter() - t0
+        span = max(r[1] for r in res)
+        allv = BYTES_PER_APPLY_PER_N * n * sum(r[0] for r in res) / span / 1e9
+        out.update(value=allv, cores=nproc,
+                   sample=f"{nproc} host processes at once, each running 2 oracle A_r applies (numpy FFT, "
+                          f"one thread) on the same {grid[0]}^3 workload: {span:.1f} s for the slowest "
+                          f"({wall:.1f} s with medium set-up); one process alone: {el / reps * 1e3:.0f} ms "
+                          f"per apply",
+                   value_one_core=one)
+    gold = {}
+    for name, f in (("eigensolve_16", "config1_16.json"), ("eigensolve_64", "config2_64.json")):
+        try:
+            g = json.load(open(os.path.join(ROOT, "tests", "golden", f)))
+        except OSError:
+            continue
+        secs = g["seconds"]
+        if isinstance(secs, list):  # [sparse shift-invert on the 6n GEP, ARPACK + CG (1e-13) on the pencil]
+            e = {"s_shift_invert_6n_gep": round(secs[0], 1), "s_arpack_cg_pencil": round(secs[1], 1)}
+        else:
+            e = {"s_arpack_cg_pencil": round(secs, 1), "route": g["route"]}
+        e.update(grid=g["grid"], k=g["k"], nev=10, timed="stored with the golden file, not in this run",
+                 host="8-core Intel Xeon @ 2.7 GHz (build host), one process")
+        gold[name] = e
+    out["oracle_eigensolve"] = gold
+    return out
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 # Sources the A_r apply kernels are compiled from (the passes and their shared
@@ -503,15 +653,19 @@ def main():
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="only run this many A_r applies plus a 1 GiB device copy (for rocprofv3)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a rocprofv3 kernel-stats table and exit")
-    ap.add_argument("--batch", default="uneven32",
-                    help="batched-vs-plain leg after the steps: kpath128, kpath128warm, uneven32, unevenN, "
-                         "or none")
-    ap.add_argument("--gamma-sweep", action="store_true", help="CG iterations against chirality (64^3)")
+    ap.add_argument("--batch", default="kpath128,uneven32",
+                    help="comma-separated batched-vs-plain legs after the steps: kpath128, kpath128warm, "
+                         "uneven32, unevenN; or none")
+    ap.add_argument("--gamma-sweep", type=int, default=64, metavar="N",
+                    help="CG iterations against chirality at N^3 (0 skips it)")
+    ap.add_argument("--band", type=int, default=3, metavar="PER_SEG",
+                    help="the paper's 128^3 band-structure leg, PER_SEG k-points per segment of G-X-M-R-G "
+                         "(the paper uses 10; 0 skips it)")
     ap.add_argument("--nfsep", type=int, default=64, metavar="N",
                     help="NFSEP leg (lossy sphere, shift-invert Arnoldi) at N^3; 0 skips it")
     ap.add_argument("--nfsep-only", action="store_true",
                     help="run only the NFSEP leg (at --nfsep N) and print its JSON")
-    ap.add_argument("--grad", type=int, default=0, metavar="NVOX",
+    ap.add_argument("--grad", type=int, default=50, metavar="NVOX",
                     help="gradient leg at 64^3: kernel cost and central differences at NVOX voxels")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ar_apply_traffic_<workload>.json from two --pmc runs and exit")
@@ -532,6 +686,18 @@ def main():
               "split in z-slabs would need an all-to-all before and after the fused z pass",
               file=sys.stderr)
         sys.exit(2)
+
+    pool, nproc = None, 1
+    if not args.no_cpu and not args.nfsep_only and not args.profile_applies:
+        # host processes for the all-cores CPU baseline, started (and idle) before
+        # anything touches the GPU
+        import concurrent.futures
+        import multiprocessing
+
+        nproc = host_workers()
+        if nproc > 1:
+            pool = concurrent.futures.ProcessPoolExecutor(nproc, mp_context=multiprocessing.get_context("spawn"))
+            list(pool.map(_oracle_apply_worker, [None] * nproc))
 
     import torch
 
@@ -652,20 +818,25 @@ def main():
     }
     if not args.no_extra:
         line["other_configs"] = extra_workloads()
-    if args.batch == "kpath128warm":
-        line["batch"] = kpath_warm_leg()
-    elif args.batch != "none":
-        line["batch"] = batch_leg(args.batch)
+    batches = []
+    for name in [b for b in args.batch.split(",") if b and b != "none"]:
+        batches.append(kpath_warm_leg() if name == "kpath128warm" else batch_leg(name))
+    if batches:
+        line["batch"] = batches[0] if len(batches) == 1 else batches
     if args.grad:
         line["grad"] = grad_leg(args.grad)
+    if args.band:
+        line["band"] = band_leg(args.band)
     if args.gamma_sweep:
-        line["gamma_sweep"] = gamma_sweep_leg()
+        line["gamma_sweep"] = gamma_sweep_leg(args.gamma_sweep)
     if args.nfsep:
         line["nfsep"] = nfsep_leg(args.nfsep)
+    P.close()
     if not args.no_cpu:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, eps, gam)
-    P.close()
+        line["cpu_baseline"] = cpu_baseline(w, eps, gam, pool, nproc)
+    if pool is not None:
+        pool.shutdown()
     print(json.dumps(line), flush=True)
 
 

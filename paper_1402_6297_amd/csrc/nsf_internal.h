@@ -381,7 +381,7 @@ struct nsf_plan_s {
   int opt_ortho_gate = 1;   // skip negligible Gram-Schmidt updates on the device
   int opt_gmres_restart = 12;  // GMRES restart length of the NFSEP eigensolver
   int opt_palette = 1;      // general / NFSEP media: palette of distinct voxel factors
-  int opt_cg_relax = 1;     // eigensolver inner CG tolerance relaxed with the Ritz residuals
+  int opt_cg_relax = 0;     // eigensolver inner CG tolerance relaxed with the Ritz residuals
 
   std::string last_error;
 };

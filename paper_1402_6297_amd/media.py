@@ -256,6 +256,21 @@ def kpath_gxmgr(per_segment: int = 10):
     return np.array(ks)
 
 
+def kpath_gxmrg(per_segment: int = 10):
+    """Bloch vectors on G-X-M-R-G (the band-structure path of the paper's Sec. 5),
+    sampled at segment midpoints as in ``kpath_gxmgr``."""
+    G = np.array([0.0, 0.0, 0.0])
+    X = np.array([0.5, 0.0, 0.0])
+    M = np.array([0.5, 0.5, 0.0])
+    R = np.array([0.5, 0.5, 0.5])
+    ks = []
+    for p, q in ((G, X), (X, M), (M, R), (R, G)):
+        for j in range(per_segment):
+            t = (j + 0.5) / per_segment
+            ks.append(p + t * (q - p))
+    return np.array(ks)
+
+
 def uneven_batch(count: int = 32, seed: int = 0, grids=(48, 64, 96, 128)):
     """Mixed-size batch of chiral-sphere instances.
 

