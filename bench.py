@@ -802,6 +802,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(apply_gbps, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(apply_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "A_r apply (all five kernels of one apply, 336 n B algorithmic; median of 100 applies timed with HIP events)",
+                     "traffic_note": "bytes per apply between the L2 caches and the memory fabric (HBM plus the "
+                                     "Infinity Cache), rocprofv3 FETCH_SIZE + WRITE_SIZE calibrated on a 1 GiB copy",
                      "kernel_us": [round(x * 1e3, 2) for x in pass_ms]},
         "device": dev_info,
         "autotune": tuned,
