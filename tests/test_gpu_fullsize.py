@@ -60,6 +60,45 @@ def test_eigs_sphere128_as_benchmarked():
     check_pencil_pairs(om, res, Y, (0, nev - 1), grid, k, tens, 1e-8)
 
 
+@pytest.mark.parametrize("eps_i,eps_o,gamma,kidx", [(13.0, 1.0, 0.5, 4), (1.0, 1.0, 0.8, 10)],
+                         ids=["eps13-gamma0.5-X-M", "eps1-gamma0.8-R-G"])
+def test_band_path_point_as_benchmarked(eps_i, eps_o, gamma, kidx):
+    """The paper's band-structure workload (spheres joined by cylinders, 128^3): one
+    k-point of the benchmarked G-X-M-R-G path (3 per segment) for each medium, nev 10,
+    residual 1e-8, CG 1e-10, multiplicity check on, as in the benchmark's band leg."""
+    grid, nev = (128, 128, 128), 10
+    n = 128 ** 3
+    k = tuple(media.kpath_gxmrg(3)[kidx])
+    eps, gam = media.spheres_cylinders_chiral(128, eps_in=eps_i, eps_out=eps_o, gamma=gamma)
+    tens = medium.tensors_chiral(eps, gam)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        P.set_option(nsf.NSF_OPT_VERIFY, 16)
+        Y = torch.empty((nev, 4 * n), dtype=torch.complex128, device="cuda")
+        st, om, res, stats = P.eigs(nev, res_tol=1e-8, cg_rtol=1e-10, Y=Y)
+    assert st == nsf.NSF_OK and res.max() <= 1e-8
+    assert np.all(om > 0) and np.all(np.diff(om) >= 0)
+    check_pencil_pairs(om, res, Y, (0, nev - 1), grid, k, tens, 1e-8)
+
+
+def test_gamma_sweep_point_64_near_singular_phi():
+    """The chirality sweep's hardest point as benchmarked: eps_i = 1, gamma = 0.9
+    (Phi = 0.19 inside), k = (1/2, 0, 0), 64^3, multiplicity check on; sampled
+    pairs recomputed by the oracle."""
+    grid, k, nev = (64, 64, 64), (0.5, 0.0, 0.0), 10
+    n = 64 ** 3
+    eps, gam = media.spheres_cylinders_chiral(64, eps_in=1.0, eps_out=1.0, gamma=0.9)
+    tens = medium.tensors_chiral(eps, gam)
+    with nsf.Plan(grid, k) as P:
+        P.set_chiral(eps, gam)
+        P.set_option(nsf.NSF_OPT_VERIFY, 16)
+        Y = torch.empty((nev, 4 * n), dtype=torch.complex128, device="cuda")
+        st, om, res, stats = P.eigs(nev, res_tol=1e-8, cg_rtol=1e-10, Y=Y)
+    assert st == nsf.NSF_OK and res.max() <= 1e-8
+    assert stats["cg_iters_avg"] > 40  # the ill-conditioned systems of the sweep's end
+    check_pencil_pairs(om, res, Y, range(nev), grid, k, tens, 1e-8)
+
+
 def test_eigs_rods128_kpath_point_as_benchmarked():
     """Pseudochiral x-y rods (eps 13, gamma 0.4, r 0.2) at 128^3, the 16th point of
     the benchmarked Gamma-X-M-Gamma-R path (on X-M): nev 10, residual 1e-8, CG
