@@ -205,6 +205,16 @@ __device__ __forceinline__ void st_off(double2* __restrict__ base, unsigned off,
   *reinterpret_cast<double2*>(reinterpret_cast<char*>(base) + (off << 4)) = v;
 }
 
+// Nontemporal store, for the CG vectors x, p, r: each is read back only in the
+// next CG iteration, after gigabytes of other traffic, so keeping it in the
+// caches gains nothing.  (The fields between passes keep plain stores: the
+// next pass finds part of them in the Infinity Cache.)
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  const v2d t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<v2d*>(p));
+}
+
 __device__ __forceinline__ void basis_at(const double2* __restrict__ lam, const Geom& g, int i1, int i2,
                                 int i3, Basis& B) {
   const double2 l1 = lam[i1], l2 = lam[g.n1 + i2], l3 = lam[g.n1 + g.n2 + i3];

@@ -456,8 +456,8 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
           const long long o = b * n + f;
           const double2 xv = make_double2(xo[b].x + cg_al * po[b].x, xo[b].y + cg_al * po[b].y);
           const double2 pn = make_double2(ro[b].x + cg_be * po[b].x, ro[b].y + cg_be * po[b].y);
-          cg.x[o] = xv;
-          cg.p[o] = pn;
+          st_stream(cg.x + o, xv);
+          st_stream(cg.p + o, pn);
           yv[b] = pn;
         }
       } else if (cg_iter > 0) {
@@ -473,9 +473,9 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
           const double2 rv = make_double2(ro[b].x - cg_al * qo[b].x, ro[b].y - cg_al * qo[b].y);
           const double2 xv = make_double2(xo[b].x + cg_al * po[b].x, xo[b].y + cg_al * po[b].y);
           const double2 pn = make_double2(rv.x + cg_be * po[b].x, rv.y + cg_be * po[b].y);
-          cg.r[o] = rv;
-          cg.x[o] = xv;
-          cg.p[o] = pn;
+          st_stream(cg.r + o, rv);
+          st_stream(cg.x + o, xv);
+          st_stream(cg.p + o, pn);
           rr_acc[0] += cabs2(rv);
           yv[b] = pn;
         }
@@ -551,8 +551,8 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
           const double2 po = a0[it][b];
           const double2 xv = make_double2(a2[it][b].x + cg_al * po.x, a2[it][b].y + cg_al * po.y);
           const double2 pn = make_double2(a1[it][b].x + cg_be * po.x, a1[it][b].y + cg_be * po.y);
-          cg.x[o] = xv;
-          cg.p[o] = pn;
+          st_stream(cg.x + o, xv);
+          st_stream(cg.p + o, pn);
           yv[b] = pn;
         }
       } else {
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const double2 rn = make_double2(rv[b].x - qf_al * qv[b].x, rv[b].y - qf_al * qv[b].y);
-          cg.r[b * n + f] = rn;
+          st_stream(cg.r + b * n + f, rn);
           acc[0] += cabs2(rn);
         }
       } else if (CG) {
