@@ -145,7 +145,7 @@ enum {
                             16-bit index per voxel when there are at most
                             4096 of them (default; piecewise-constant media),
                             0 always stores one factor per voxel           */
-  NSF_OPT_CG_RELAX = 12  /* eigensolver inner CG tolerance (nsf_eigs,
+  NSF_OPT_CG_RELAX = 12,  /* eigensolver inner CG tolerance (nsf_eigs,
                             nsf_batch_eigs): 0 (default) solves every system
                             to cg_rtol; 1 relaxes the solves as the Ritz
                             residuals fall (relaxation of inexact Krylov
@@ -159,6 +159,15 @@ enum {
                             to Gamma stalled.  The projected matrix is exact
                             and the returned pairs are checked with exact
                             applies either way                               */
+  NSF_OPT_WARM_CHAIN = 13 /* nsf_batch_eigs, set on instance i (default 0):
+                            when instance i - 1 has the same grid and was
+                            solved in an earlier wave (every instance of
+                            2^21 voxels or more is a wave of its own), the
+                            Lanczos start of instance i combines the Ritz
+                            vectors of instance i - 1 (as nsf_eigs_set_start),
+                            which saves steps along a path of nearby k-points;
+                            results are checked by their own residuals as
+                            for any start                                    */
 };
 
 /*

@@ -1088,6 +1088,21 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
     waves.emplace_back(shared.begin() + w0, shared.begin() + std::min(shared.size(), w0 + (size_t)wave));
   for (int i : solo) waves.push_back({i});
   int worst = NSF_OK;
+  // NSF_OPT_WARM_CHAIN: the Ritz vectors of the instance solved last, kept for
+  // the next instance when that one asks for them and has the same grid
+  double2* chain = nullptr;
+  size_t chain_bytes = 0;
+  int chain_from = -1;
+  auto same_grid = [&](int i, int j) {
+    const Geom &a = b->plans[i]->geom, &c = b->plans[j]->geom;
+    return a.n1 == c.n1 && a.n2 == c.n2 && a.n3 == c.n3;
+  };
+  struct ChainFree {
+    double2** ptr;
+    ~ChainFree() {
+      if (*ptr) hipFree(*ptr);
+    }
+  } chain_free{&chain};
   for (size_t wv = 0; wv < waves.size(); ++wv) {
     const std::vector<int>& ids = waves[wv];
     std::vector<Run> runs(ids.size());
@@ -1096,6 +1111,10 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
       const int i = ids[j];
       nsf_plan p = b->plans[i];
       p->stream = b->stream;
+      if (p->opt_warm_chain && chain && chain_from == i - 1 && same_grid(i, i - 1)) {
+        p->start_Y = chain;
+        p->start_count = nev;
+      }
       const int rc = make_run(p, nev, res_tol, cg_rtol, max_basis, max_restarts, seed + 1000003ULL * i, runs[j]);
       if (rc) return set_error(nullptr, rc, "instance " + std::to_string(i) + ": " + p->last_error);
       ptrs.push_back(&runs[j]);
@@ -1111,6 +1130,20 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
       if (Y_dev && Y_dev[i])
         NSF_HIP(r.p, hipMemcpyAsync(Y_dev[i], r.V, sizeof(double2) * (size_t)nev * r.len, hipMemcpyDeviceToDevice,
                                     b->stream));
+      // instance i + 1 runs in a later wave (waves keep index order within the
+      // shared and the solo instances)
+      if (i + 1 < B && b->plans[i + 1]->opt_warm_chain && same_grid(i, i + 1) &&
+          std::find(ids.begin(), ids.end(), i + 1) == ids.end()) {
+        const size_t bytes = sizeof(double2) * (size_t)nev * r.len;
+        if (bytes > chain_bytes) {
+          if (chain) NSF_HIP(r.p, hipFree(chain));
+          chain = nullptr;
+          NSF_HIP(r.p, hipMalloc(&chain, bytes));
+          chain_bytes = bytes;
+        }
+        NSF_HIP(r.p, hipMemcpyAsync(chain, r.V, bytes, hipMemcpyDeviceToDevice, b->stream));
+        chain_from = i;
+      }
     }
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     for (size_t j = 0; j < ids.size(); ++j) {

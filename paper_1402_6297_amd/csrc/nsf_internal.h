@@ -382,6 +382,7 @@ struct nsf_plan_s {
   int opt_gmres_restart = 12;  // GMRES restart length of the NFSEP eigensolver
   int opt_palette = 1;      // general / NFSEP media: palette of distinct voxel factors
   int opt_cg_relax = 0;     // eigensolver inner CG tolerance relaxed with the Ritz residuals
+  int opt_warm_chain = 0;   // nsf_batch_eigs: start from the previous instance's Ritz vectors
 
   std::string last_error;
 };

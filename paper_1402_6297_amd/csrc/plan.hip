@@ -448,6 +448,10 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_RELAX takes 0 or 1");
       p->opt_cg_relax = value;
       return NSF_OK;
+    case NSF_OPT_WARM_CHAIN:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_WARM_CHAIN takes 0 or 1");
+      p->opt_warm_chain = value;
+      return NSF_OK;
     case NSF_OPT_CG_GRAPH:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_GRAPH takes 0 or 1");
       p->opt_cg_graph = value;

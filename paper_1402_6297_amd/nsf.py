@@ -44,6 +44,7 @@ NSF_OPT_ORTHO_GATE = 9
 NSF_OPT_GMRES_RESTART = 10
 NSF_OPT_MEDIUM_PALETTE = 11
 NSF_OPT_CG_RELAX = 12
+NSF_OPT_WARM_CHAIN = 13
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",

@@ -6,6 +6,7 @@
 * the band-structure media of Sec. 5, (eps_i, eps_o, gamma) = (13, 1, 0.5) and
   (1, 1, 0.8), at a generic k and at k-points of the G-X-M-R-G path;
 * the relaxed inner CG tolerance (NSF_OPT_CG_RELAX) against fixed-tolerance solves;
+* batch instances chained along a k-path (NSF_OPT_WARM_CHAIN) against cold solves;
 * multiple eigenvalues (air at a k on a lattice axis): every copy from the batch
   path and from the differentiable wrapper, and with default options only true
   eigenvalues.
@@ -124,6 +125,32 @@ def test_relaxed_inner_tolerance_batch_matches_plain():
             P.set_option(nsf.NSF_OPT_CG_RELAX, 0)
             st1, om1, _, _ = P.eigs(8, res_tol=1e-8, cg_rtol=1e-10)
         assert st1 == nsf.NSF_OK and close(om[i], om1)
+
+
+def test_warm_chain_batch_matches_cold_solves():
+    """Three consecutive k-points of the 128^3 rods path (each 128^3 instance runs
+    in a wave of its own): with NSF_OPT_WARM_CHAIN the second and third start from
+    their predecessor's Ritz vectors, reach the same eigenvalues as cold plain
+    solves and take fewer Lanczos steps."""
+    g, nev = (128, 128, 128), 10
+    ks = [tuple(k) for k in media.kpath_gxmgr(10)[14:17]]
+    eps, gam = media.rods_pseudochiral(128)
+    kw = dict(res_tol=1e-8, cg_rtol=1e-10, seed=0)
+    with nsf.Batch([g] * 3, ks) as B:
+        for i in range(3):
+            B.set_pseudochiral(i, 0, 1, eps, gam)
+            nsf.nsf_plan_set_option(B.plan(i), nsf.NSF_OPT_WARM_CHAIN, int(i > 0))
+        st, om, res, stats, wave = B.eigs(nev, **kw)
+    assert st == nsf.NSF_OK and res.max() <= 1e-8 and wave == 1
+    for i, k in enumerate(ks):
+        with nsf.Plan(g, k) as P:
+            P.set_pseudochiral(0, 1, eps, gam)
+            st1, om1, _, s1 = P.eigs(nev, **kw)
+        assert st1 == nsf.NSF_OK and close(om[i], om1, 1e-9), (i, om[i], om1)
+        if i == 0:
+            assert stats[0]["lanczos_steps"] == s1["lanczos_steps"]  # same cold start
+        else:
+            assert stats[i]["lanczos_steps"] < s1["lanczos_steps"], (stats[i], s1)
 
 
 # ------------------------------------------------------- multiple eigenvalues
