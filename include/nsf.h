@@ -159,7 +159,7 @@ enum {
                             to Gamma stalled.  The projected matrix is exact
                             and the returned pairs are checked with exact
                             applies either way                               */
-  NSF_OPT_WARM_CHAIN = 13 /* nsf_batch_eigs, set on instance i (default 0):
+  NSF_OPT_WARM_CHAIN = 13,/* nsf_batch_eigs, set on instance i (default 0):
                             when instance i - 1 has the same grid and was
                             solved in an earlier wave (every instance of
                             2^21 voxels or more is a wave of its own), the
@@ -168,6 +168,17 @@ enum {
                             which saves steps along a path of nearby k-points;
                             results are checked by their own residuals as
                             for any start                                    */
+  NSF_OPT_CG_RING = 14    /* 1 (default): the q-free fused CG (chiral and
+                            pseudochiral media on the fast passes, plan
+                            memory) keeps its last 16 directions p_j on the
+                            device and adds x += sum alpha_j p_j once every
+                            16 iterations and at the end of the solve,
+                            instead of reading and writing x in every
+                            iteration (128 n bytes less per iteration,
+                            16 x 64 n bytes of device memory more); the
+                            residual recurrence is unchanged, so iterations
+                            and residuals are the same and x differs only in
+                            rounding.  0: x updated every iteration       */
 };
 
 /*

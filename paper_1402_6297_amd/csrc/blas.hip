@@ -124,10 +124,12 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_init(const double2* __restri
 
 __global__ __launch_bounds__(kRedThreads) void k_cg_init_final(const double2* partial, int nparts,
                                                                CgState* st, double rtol,
-                                                               int maxit) {
+                                                               int maxit, int ring) {
   const double2 s = fold_partials(partial, nparts);
   if (threadIdx.x == 0) {
     const double bb = s.x;
+    st->ring = ring;
+    st->bd_step = 0;
     st->bb = bb;
     st->rr = s.y;
     st->thresh = rtol * rtol * bb;
@@ -310,11 +312,14 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_step_qf(const double* part,
   if (threadIdx.x == 0) {
     const double pap = st->pap, rr = st->rr, rn = v.x;
     if (!(pap > 0.0) || !isfinite(pap)) {  // the last pass left r unchanged
+      if (st->ring > 0) st->ahist[st->iter % st->ring] = 0.0;  // its p is not folded in
+      st->bd_step = 1;
       st->status = NSF_E_BREAKDOWN;
       st->done = 1;
       return;
     }
     st->alpha = rr / pap;
+    if (st->ring > 0) st->ahist[st->iter % st->ring] = st->alpha;
     st->beta = rn / rr;
     st->rr = rn;
     st->iter += 1;
@@ -342,6 +347,55 @@ __global__ void k_cg_finish(double2* __restrict__ x, const double2* __restrict__
     const double2 pv = p[i];
     const double2 xv = x[i];
     x[i] = make_double2(xv.x + al * pv.x, xv.y + al * pv.y);
+  }
+}
+
+// Kept directions of the q-free CG: x += sum_j alpha_j p_j over ring slots
+// [0, cnt).  final = false runs inside iteration k = st->iter, after its alpha
+// is known (rr / pap), and folds the whole ring when k + 1 fills it; final =
+// true runs once after the solve and folds the slots written since the last
+// fold (an iteration that broke down has alpha 0 in the history).
+__global__ __launch_bounds__(256) void k_cg_fold(double2* __restrict__ x, const double2* __restrict__ ring,
+                                                 long long len, const CgState* st, int final,
+                                                 const InstDesc* __restrict__ insts) {
+  if (insts) {
+    const CgFuse& cg = insts[blockIdx.z].cg;
+    x = cg.x;
+    ring = cg.ring;
+    st = cg.st;
+  }
+  const int K = st->ring;
+  if (K <= 0) return;
+  double a[kCgRing];
+  int cnt;
+  if (!final) {
+    if (st->done) return;
+    const int k = st->iter;
+    if ((k + 1) % K != 0) return;
+    const double pap = st->pap;
+    const double ak = (pap > 0.0 && isfinite(pap)) ? st->rr / pap : 0.0;  // this iteration's alpha
+#pragma unroll
+    for (int j = 0; j < kCgRing; ++j) a[j] = j < K - 1 ? st->ahist[j] : (j == K - 1 ? ak : 0.0);
+    cnt = K;
+  } else {
+    const int nit = st->iter + (st->status == NSF_E_BREAKDOWN ? st->bd_step : 0);
+    cnt = nit % K;
+    if (cnt == 0) return;
+#pragma unroll
+    for (int j = 0; j < kCgRing; ++j) a[j] = j < cnt ? st->ahist[j] : 0.0;
+  }
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x) {
+    double2 acc = x[i];
+#pragma unroll
+    for (int j = 0; j < kCgRing; ++j) {
+      if (j < cnt) {
+        const double2 pv = ring[(long long)j * len + i];
+        acc.x += a[j] * pv.x;
+        acc.y += a[j] * pv.y;
+      }
+    }
+    x[i] = acc;
   }
 }
 
@@ -567,11 +621,12 @@ hipError_t launch_reduce_partials(const double2* partial, int nparts, double2* o
 
 hipError_t launch_cg_init(const double2* b, double2* x, double2* r, double2* p, long long len,
                           double2* partial, CgState* st, double rtol, int maxit, hipStream_t s,
-                          const double2* AV, long long ld, int m, const double2* c) {
+                          const double2* AV, long long ld, int m, const double2* c, int ring) {
   if (m < 0 || m > 512 || (m > 0 && (!AV || !c))) return hipErrorInvalidValue;
+  if (ring < 0 || ring > kCgRing) return hipErrorInvalidValue;
   const int nb = red_grid(len);
   hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, b, x, r, p, len, partial, AV, ld, m, c);
-  hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kRedThreads), 0, s, partial, nb, st, rtol, maxit);
+  hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kRedThreads), 0, s, partial, nb, st, rtol, maxit, ring);
   return hipGetLastError();
 }
 
@@ -624,6 +679,15 @@ hipError_t launch_cgf_step_qf(const double* part_out, int nparts, CgState* st, h
 
 hipError_t launch_cg_finish(double2* x, const double2* p, long long len, const CgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_finish, dim3(ew_grid(len)), dim3(256), 0, s, x, p, len, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_fold(double2* x, const double2* ring, long long len, const CgState* st, bool final,
+                          hipStream_t s, const InstDesc* insts, int ninst) {
+  // a grid of 1024 workgroups: the launch inside every iteration returns at
+  // once except when the ring is full
+  const dim3 grid((unsigned)std::min(ew_grid(len), 1024), 1, (unsigned)ninst);
+  hipLaunchKernelGGL(k_cg_fold, grid, dim3(256), 0, s, x, ring, len, st, final ? 1 : 0, insts);
   return hipGetLastError();
 }
 

@@ -426,10 +426,24 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   double rr_acc[1] = {0.0};
   int cg_iter = 0;
   double cg_al = 0, cg_be = 0;
+  // p of the previous iteration is read from pin and the new p written to
+  // pout: the same vector, or (q-free with kept directions) ring slots
+  // (k - 1) mod K and k mod K, in which case x is not updated here
+  const double2* pin = nullptr;
+  double2* pout = nullptr;
+  bool ring = false;
   if (CG) {
     cg_iter = cg.st->iter;
     cg_al = cg.st->alpha;
     cg_be = cg.st->beta;
+    pin = cg.p;
+    pout = cg.p;
+    const int K = QF && cg.ring ? cg.st->ring : 0;
+    if (K > 0) {
+      ring = true;
+      pin = cg.ring + (long long)((cg_iter > 0 ? cg_iter - 1 : 0) % K) * 4 * g.n;
+      pout = cg.ring + (long long)(cg_iter % K) * 4 * g.n;
+    }
   }
   // synthesis of the coefficient fields at frequency slot e of the workgroup
   auto synth = [&](int e) {
@@ -444,20 +458,19 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
       // every load is issued before the stores (which may alias them)
       double2 po[4], qo[4], ro[4], xo[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) po[b] = cg.p[b * n + f];
+      for (int b = 0; b < 4; ++b) po[b] = pin[b * n + f];
       if (QF && cg_iter > 0) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           ro[b] = cg.r[b * n + f];
-          xo[b] = cg.x[b * n + f];
+          if (!ring) xo[b] = cg.x[b * n + f];
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const long long o = b * n + f;
-          const double2 xv = make_double2(xo[b].x + cg_al * po[b].x, xo[b].y + cg_al * po[b].y);
           const double2 pn = make_double2(ro[b].x + cg_be * po[b].x, ro[b].y + cg_be * po[b].y);
-          st_stream(cg.x + o, xv);
-          st_stream(cg.p + o, pn);
+          if (!ring) st_stream(cg.x + o, make_double2(xo[b].x + cg_al * po[b].x, xo[b].y + cg_al * po[b].y));
+          st_stream(pout + o, pn);
           yv[b] = pn;
         }
       } else if (cg_iter > 0) {
@@ -526,12 +539,12 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
       fo[it] = (row0 + r) * N + i1;
       if (ok[it]) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) a0[it][b] = CG ? cg.p[b * n + fo[it]] : y[b * n + fo[it]];
+        for (int b = 0; b < 4; ++b) a0[it][b] = CG ? pin[b * n + fo[it]] : y[b * n + fo[it]];
         if (upd) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             a1[it][b] = cg.r[b * n + fo[it]];
-            a2[it][b] = cg.x[b * n + fo[it]];
+            if (!ring) a2[it][b] = cg.x[b * n + fo[it]];
           }
         }
       }
@@ -549,10 +562,10 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
         for (int b = 0; b < 4; ++b) {
           const long long o = b * n + f;
           const double2 po = a0[it][b];
-          const double2 xv = make_double2(a2[it][b].x + cg_al * po.x, a2[it][b].y + cg_al * po.y);
           const double2 pn = make_double2(a1[it][b].x + cg_be * po.x, a1[it][b].y + cg_be * po.y);
-          st_stream(cg.x + o, xv);
-          st_stream(cg.p + o, pn);
+          if (!ring)
+            st_stream(cg.x + o, make_double2(a2[it][b].x + cg_al * po.x, a2[it][b].y + cg_al * po.y));
+          st_stream(pout + o, pn);
           yv[b] = pn;
         }
       } else {

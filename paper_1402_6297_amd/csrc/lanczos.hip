@@ -169,6 +169,7 @@ int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
                                   nullptr, &npm));
     if ((npm > 0) != qf) return set_error(p0, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
     if (qf) NSF_HIP(p0, launch_cgf_alpha(nullptr, npm, nullptr, s, d, na));
+    if (qf) NSF_HIP(p0, launch_cg_fold(nullptr, nullptr, 4 * g.n, nullptr, false, s, d, na));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, qf));
     if (qf)
@@ -285,8 +286,11 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
       if (m) NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * 2 * m, hipMemcpyHostToDevice, s));
     }
     r->start_m = m;
-    NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, p->d_cg + r->len, r->len, p->d_partial, p->d_state,
-                              r->cg_tol, 5000, s, m ? r->AV : nullptr, r->len, m, m ? p->d_coef : nullptr));
+    // kept directions when this run iterates q-free and its plan holds them
+    const bool ring = p->d_ring && qfree_of(groups, r);
+    NSF_HIP(p, launch_cg_init(r->bv, r->w, p->d_cg, ring ? p->d_ring : p->d_cg + r->len, r->len, p->d_partial,
+                              p->d_state, r->cg_tol, 5000, s, m ? r->AV : nullptr, r->len, m,
+                              m ? p->d_coef : nullptr, ring ? kCgRing : 0));
   }
   bool graph = cgg != nullptr && !debug_sync();
   for (Run* r : act) graph = graph && r->p->opt_cg_graph;
@@ -340,7 +344,9 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
     r->st.matvecs += h.iter;
     if (h.status == NSF_E_BREAKDOWN)
       return set_error(r->p, NSF_E_BREAKDOWN, "CG breakdown: p^* A_r p <= 0 or not finite");
-    if (qfree_of(groups, r))  // the final x = x + alpha p (ws has drained)
+    if (qfree_of(groups, r) && r->p->d_ring)  // the directions since the last fold (ws has drained)
+      NSF_HIP(r->p, launch_cg_fold(r->w, r->p->d_ring, r->len, r->p->d_state, true, s));
+    else if (qfree_of(groups, r))  // the final x = x + alpha p
       NSF_HIP(r->p, launch_cg_finish(r->w, r->p->d_cg + r->len, r->len, r->p->d_state, s));
   }
   return NSF_OK;
@@ -810,6 +816,8 @@ int make_run(nsf_plan p, int nev, double res_tol, double cg_rtol, int max_basis,
   if (m < nev + 2) return set_error(p, NSF_E_ARG, "grid too small for nev");
   int rc = ensure_cg(p);
   if (rc) return rc;
+  rc = ensure_ring(p, cg_qfree(p));
+  if (rc) return rc;
   rc = ensure_basis(p, (size_t)m + 1);
   if (rc) return rc;
   rc = ensure_small(p, (size_t)m * m);
@@ -1065,7 +1073,8 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
   // streams HBM at 5-6 TB/s), so sharing launches would only add lock-step
   // waits: each runs as a wave of its own, exactly as nsf_eigs.  The others
   // run in shared waves that fit in device memory: fields 6n, CG and Lanczos
-  // vectors 6 x 4n, basis 2 (m+1) x 4n, medium n complex each.
+  // vectors 6 x 4n, kept CG directions kCgRing x 4n, basis 2 (m+1) x 4n, medium
+  // n complex each.
   const int m = max_basis > 0 ? max_basis : std::max(3 * nev, nev + 8);
   size_t free_b = 0, total_b = 0;
   NSF_HIP(b->plans[0], hipMemGetInfo(&free_b, &total_b));
@@ -1078,7 +1087,7 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
       continue;
     }
     shared.push_back(i);
-    need_max = std::max(need_max, 16.0 * n * (6 + 24 + 8.0 * (m + 1) + 1) + (64 << 20));
+    need_max = std::max(need_max, 16.0 * n * (6 + 24 + 4.0 * kCgRing + 8.0 * (m + 1) + 1) + (64 << 20));
   }
   int wave = shared.empty() ? 1 : (int)std::max(1.0, std::floor(0.85 * (double)free_b / need_max));
   wave = std::min(wave, std::max((int)shared.size(), 1));
@@ -1165,6 +1174,8 @@ int nsf_batch_eigs(nsf_batch b, int nev, double res_tol, double cg_rtol, int max
         p->basis_vectors = 0;
         if (p->d_cg) NSF_HIP(p, hipFree(p->d_cg));
         p->d_cg = nullptr;
+        if (p->d_ring) NSF_HIP(p, hipFree(p->d_ring));
+        p->d_ring = nullptr;
       }
   }
   return worst;

@@ -171,6 +171,10 @@ constexpr int kCoefSlots = 1024;       // device coefficient vector of the Lancz
 constexpr int kResSlots = 1100;        // reduction results (and host copies of coefficients)
 constexpr int kMidSlots = 32768;       // doubles x 2: partials of the fused z pass
 
+// Directions kept by the q-free CG in place of updating x every iteration:
+// x = x0 + sum_j alpha_j p_j is folded in every kCgRing iterations.
+constexpr int kCgRing = 16;
+
 struct CgState {
   double rr;        // r^* r of the current iterate
   double thresh;    // (rtol ||b||)^2
@@ -179,8 +183,11 @@ struct CgState {
   int iter, maxit;
   int done;         // nonzero: every CG kernel exits at once
   int status;       // NSF_OK / NSF_NOT_CONVERGED / NSF_E_BREAKDOWN
-  int pad[3];
+  int ring;         // directions kept (0: x is updated every iteration)
+  int bd_step;      // 1: the breakdown happened inside an iteration (its p was written)
+  int pad;
   double pap;       // p^* A_r p of the current direction (q-free fused schedule)
+  double ahist[kCgRing];  // alpha_j of the kept directions, slot j mod ring
 };
 
 // Vectors and device scalars of a CG solve whose recurrences are fused into
@@ -190,6 +197,7 @@ struct CgFuse {
   double2* r;
   double2* p;
   double2* q;
+  double2* ring;     // q-free with kept directions: slot j (4n each) holds p_j, j mod ring
   CgState* st;
   double* part_in;   // per-workgroup |r|^2 of the first pass
   double* part_out;  // per-workgroup (Re p^*q, |q|^2, Re r^*q) of the last pass
@@ -256,17 +264,25 @@ hipError_t launch_cgf_alpha(const double* part_mid, int np_mid, CgState* st, hip
 hipError_t launch_cgf_step_qf(const double* part_out, int nparts, CgState* st, hipStream_t s,
                               const InstDesc* insts = nullptr, int ninst = 1);
 hipError_t launch_cg_finish(double2* x, const double2* p, long long len, const CgState* st, hipStream_t s);
+// Kept directions (CgState::ring > 0): x += sum alpha_j p_j over the ring.
+// final = false, inside an iteration after launch_cgf_alpha: folds all ring
+// slots when this iteration fills the ring (its alpha = rr / pap, 0 when pap
+// is not positive).  final = true, once the solve has ended: folds the slots
+// written since the last fold.  Batched form: x, ring, st from insts[i].cg.
+hipError_t launch_cg_fold(double2* x, const double2* ring, long long len, const CgState* st, bool final,
+                          hipStream_t s, const InstDesc* insts = nullptr, int ninst = 1);
 
 // partial[blk] = sum conj(x) y over a fixed slice (complex, as double2).
 hipError_t launch_dot_partials(const double2* x, const double2* y, long long len,
                                double2* partial, const int* skip, hipStream_t s);
 // x = 0 and r = p = b - sum_{j<m} c_j AV_{idx_j} (c on device: m coefficients,
 // then the m indices as doubles in .x; m <= 512; plain r = b when m = 0); the
-// stopping threshold stays relative to ||b||.
+// stopping threshold stays relative to ||b||.  ring > 0: the q-free CG keeps
+// that many directions (p is then ring slot 0).
 hipError_t launch_cg_init(const double2* b, double2* x, double2* r, double2* p, long long len,
                           double2* partial, CgState* st, double rtol, int maxit, hipStream_t s,
                           const double2* AV = nullptr, long long ld = 0, int m = 0,
-                          const double2* c = nullptr);
+                          const double2* c = nullptr, int ring = 0);
 hipError_t launch_cg_alpha(const double2* partial, int nparts, CgState* st, hipStream_t s);
 hipError_t launch_cg_update(double2* x, double2* r, const double2* p, const double2* q,
                             long long len, double2* partial, CgState* st, hipStream_t s);
@@ -383,6 +399,8 @@ struct nsf_plan_s {
   int opt_palette = 1;      // general / NFSEP media: palette of distinct voxel factors
   int opt_cg_relax = 0;     // eigensolver inner CG tolerance relaxed with the Ritz residuals
   int opt_warm_chain = 0;   // nsf_batch_eigs: start from the previous instance's Ritz vectors
+  int opt_cg_ring = 1;      // q-free CG keeps kCgRing directions instead of updating x
+  double2* d_ring = nullptr;  // those directions, kCgRing x 4n
 
   std::string last_error;
 };
@@ -427,6 +445,7 @@ size_t workspace_bytes(long long n, int m);
 // vectors to *basis_cap), 3 small matrices; nullptr when the plan has none.
 double2* ws_part(nsf_plan p, int which, size_t* basis_cap = nullptr);
 int ensure_cg(nsf_plan p);
+int ensure_ring(nsf_plan p, bool want);
 bool cg_fusable(nsf_plan p);
 CgFuse cg_fuse_of(nsf_plan p, double2* x, double2* cgv = nullptr);
 int cg_iteration(nsf_plan p, double2* x, bool fused, double2* cgv = nullptr);

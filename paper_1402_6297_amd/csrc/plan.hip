@@ -355,6 +355,7 @@ void nsf_plan_destroy(nsf_plan p) {
     if (p->d_mfull) hipFree(p->d_mfull);
     if (p->d_pidx) hipFree(p->d_pidx);
     if (p->d_cg && !p->ws) hipFree(p->d_cg);
+    if (p->d_ring) hipFree(p->d_ring);
     if (p->d_basis && !p->ws) hipFree(p->d_basis);
     if (p->d_small && !p->ws) hipFree(p->d_small);
   }
@@ -386,6 +387,8 @@ int nsf_plan_set_workspace(nsf_plan p, void* dev_ptr, size_t bytes) {
     if (p->d_basis) NSF_HIP(p, hipFree(p->d_basis));
     if (p->d_small) NSF_HIP(p, hipFree(p->d_small));
   }
+  if (p->d_ring) NSF_HIP(p, hipFree(p->d_ring));  // the plan's own memory in either case
+  p->d_ring = nullptr;
   p->d_fields = p->d_cg = p->d_basis = p->d_small = nullptr;
   p->basis_vectors = 0;
   p->small_cap = 0;
@@ -451,6 +454,10 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
     case NSF_OPT_WARM_CHAIN:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_WARM_CHAIN takes 0 or 1");
       p->opt_warm_chain = value;
+      return NSF_OK;
+    case NSF_OPT_CG_RING:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_RING takes 0 or 1");
+      p->opt_cg_ring = value;
       return NSF_OK;
     case NSF_OPT_CG_GRAPH:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_GRAPH takes 0 or 1");

@@ -116,10 +116,32 @@ bool cg_fusable(nsf_plan p) {
   return p->opt_fft_path != 1 && xr > 0 && ((long long)g.n2 * g.n3 + xr - 1) / xr <= 65536;
 }
 
+// Kept CG directions for the next solve of plan p: allocated when that solve
+// runs the q-free fused schedule in plan memory with NSF_OPT_CG_RING on, else
+// released (the kernels keep x updated every iteration then).  An allocation
+// failure also leaves the plan on the per-iteration x update.
+int ensure_ring(nsf_plan p, bool want) {
+  want = want && p->opt_cg_ring && !p->ws;
+  if (!want) {
+    if (p->d_ring) {
+      NSF_HIP(p, hipStreamSynchronize(p->stream));
+      NSF_HIP(p, hipFree(p->d_ring));
+      p->d_ring = nullptr;
+    }
+    return NSF_OK;
+  }
+  if (p->d_ring) return NSF_OK;
+  if (hipMalloc(&p->d_ring, sizeof(double2) * kCgRing * 4 * (size_t)p->geom.n) != hipSuccess) {
+    (void)hipGetLastError();
+    p->d_ring = nullptr;
+  }
+  return NSF_OK;
+}
+
 CgFuse cg_fuse_of(nsf_plan p, double2* x, double2* cgv) {
   const long long len = 4 * p->geom.n;
   double2* c = cgv ? cgv : p->d_cg;
-  return CgFuse{x, c, c + len, c + 2 * len, p->d_state,
+  return CgFuse{x, c, c + len, c + 2 * len, cgv ? nullptr : p->d_ring, p->d_state,
                 reinterpret_cast<double*>(p->d_partial), reinterpret_cast<double*>(p->d_partial) + 65536,
                 reinterpret_cast<double*>(p->d_partial + kPartialSlots + kCoefSlots + kResSlots)};
 }
@@ -136,7 +158,7 @@ int cg_iteration(nsf_plan p, double2* x, bool fused, double2* cgv) {
   double2* pp = r + len;
   double2* q = pp + len;
   if (fused) {
-    const CgFuse cgf = cg_fuse_of(p, x, r);
+    const CgFuse cgf = cg_fuse_of(p, x, cgv);
     const bool qf = z_mid_pq_items(p) > 0;
     int np1 = 0, np5 = 0;
     NSF_HIP(p, launch_fast_cg_first(p->geom, p->tabs, cgf, p->d_fields, skip, &np1, s, nullptr, 1, qf));
@@ -146,6 +168,7 @@ int cg_iteration(nsf_plan p, double2* x, bool fused, double2* cgv) {
     NSF_HIP(p, pass_z_mid(p, p->d_fields, skip, cgf.part_mid, &npm));
     if ((npm > 0) != qf) return set_error(p, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
     if (qf) NSF_HIP(p, launch_cgf_alpha(cgf.part_mid, npm, st, s));
+    if (qf && cgf.ring) NSF_HIP(p, launch_cg_fold(x, cgf.ring, len, st, false, s));
     NSF_HIP(p, pass_yz(p, 1, -1, 6, p->d_fields, 0, 0, skip));
     NSF_HIP(p, launch_fast_cg_last(p->geom, p->tabs, cgf, p->d_fields, skip, &np5, s, nullptr, 1, qf));
     if (qf)
@@ -191,12 +214,15 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
   hipStream_t s = p->stream;
   CgState* st = p->d_state;
   const int nparts = reduce_parts_for(len);
-  NSF_HIP(p, launch_cg_init(b, x, r, pp, len, p->d_partial, st, rtol, maxit, s));
   // Fused iterations when the x axis has a two-level pass: the CG updates
   // ride in the first and last FFT pass of every A_r apply.
   const Geom& g = p->geom;
   const bool fused = cg_fusable(p);
   const bool qf = fused && cg_qfree(p);
+  if (!cgv && (rc = ensure_ring(p, qf))) return rc;  // (caller vectors: no allocation, no ring)
+  double2* ring = cgv ? nullptr : p->d_ring;
+  NSF_HIP(p, launch_cg_init(b, x, r, ring ? ring : pp, len, p->d_partial, st, rtol, maxit, s, nullptr, 0, 0,
+                            nullptr, ring ? kCgRing : 0));
   (void)nparts;
   (void)g;
   int chunk = 4;
@@ -204,7 +230,7 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
   int it_prev = 0;
   for (;;) {
     for (int c = 0; c < chunk; ++c) {
-      rc = cg_iteration(p, x, fused, r);
+      rc = cg_iteration(p, x, fused, cgv);
       if (rc) return rc;
     }
     NSF_HIP(p, hipMemcpyAsync(p->h_state, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -215,7 +241,10 @@ int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxi
     rr_prev = h.rr;
     it_prev = h.iter;
   }
-  if (qf) NSF_HIP(p, launch_cg_finish(x, pp, len, st, s));
+  if (qf && ring)
+    NSF_HIP(p, launch_cg_fold(x, ring, len, st, true, s));
+  else if (qf)
+    NSF_HIP(p, launch_cg_finish(x, pp, len, st, s));
   const CgState& h = *p->h_state;
   if (iters) *iters = h.iter;
   if (relres) *relres = (h.bb > 0) ? std::sqrt(h.rr / h.bb) : 0.0;
