@@ -168,7 +168,7 @@ enum {
                             which saves steps along a path of nearby k-points;
                             results are checked by their own residuals as
                             for any start                                    */
-  NSF_OPT_CG_RING = 14    /* 1 (default): the q-free fused CG (chiral and
+  NSF_OPT_CG_RING = 14,   /* 1 (default): the q-free fused CG (chiral and
                             pseudochiral media on the fast passes, plan
                             memory) keeps its last 16 directions p_j on the
                             device and adds x += sum alpha_j p_j once every
@@ -179,6 +179,19 @@ enum {
                             residual recurrence is unchanged, so iterations
                             and residuals are the same and x differs only in
                             rounding.  0: x updated every iteration       */
+  NSF_OPT_VACUUM = 15     /* 1 (default): with a chiral or pseudochiral medium
+                            on the two-level passes, the field-pair z pass
+                            transforms only the tiles (P pencil columns of
+                            one y) holding a voxel other than vacuum (eps 1,
+                            gamma 0): in a vacuum column the middle factor
+                            is the identity, so inverse z, middle factor and
+                            forward z return the column unchanged once the
+                            1/n normalisation is split as 1/n3 in that pass
+                            and 1/(n1 n2) in the projection.  p^* A_r p is
+                            then |p|^2 plus the listed columns' share.  The
+                            lists are built when the medium is set.  Same
+                            operator up to rounding; 0 transforms every
+                            column                                          */
 };
 
 /*

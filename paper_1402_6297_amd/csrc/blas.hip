@@ -286,14 +286,19 @@ __global__ __launch_bounds__(kRedThreads) void k_cgf_step(const double* part, in
 }
 
 // q-free schedule, after the fused z pass: st->pap = sum of its partials.
+// With np_in > 0 (vacuum skipping) the z pass summed Re f^* (M - I) f / n only
+// and the first pass's |p|^2 partials complete p^* A_r p.
 __global__ __launch_bounds__(kRedThreads) void k_cgf_alpha(const double* part_mid, int np_mid, CgState* st,
-                                                           const InstDesc* insts) {
+                                                           const InstDesc* insts, const double* part_in,
+                                                           int np_in) {
   if (insts) {
     part_mid = insts[blockIdx.x].cg.part_mid;
     st = insts[blockIdx.x].cg.st;
+    part_in = insts[blockIdx.x].cg.part_in;
   }
   if (st->done) return;
-  double2 a = make_double2(fold_doubles(part_mid, np_mid, 1), 0);
+  double2 a = make_double2(fold_doubles(part_mid, np_mid, 1) + (np_in > 0 ? fold_doubles(part_in, np_in, 1) : 0.0),
+                           0);
   a = block_sum(a);
   if (threadIdx.x == 0) st->pap = a.x;
 }
@@ -666,8 +671,9 @@ hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipS
 }
 
 hipError_t launch_cgf_alpha(const double* part_mid, int np_mid, CgState* st, hipStream_t s,
-                            const InstDesc* insts, int ninst) {
-  hipLaunchKernelGGL(k_cgf_alpha, dim3(ninst), dim3(kRedThreads), 0, s, part_mid, np_mid, st, insts);
+                            const InstDesc* insts, int ninst, const double* part_in, int np_in) {
+  hipLaunchKernelGGL(k_cgf_alpha, dim3(ninst), dim3(kRedThreads), 0, s, part_mid, np_mid, st, insts, part_in,
+                     np_in);
   return hipGetLastError();
 }
 

@@ -223,10 +223,17 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
 // transform over k2 in registers, the twiddle w^-(k1 m2), one LDS exchange, and
 // a radix-N1 transform over k1 that yields the outputs m2 + N2 m1 at exactly the
 // addresses the thread loaded.
+// vs > 0 (vacuum skipping): the workgroups cover only the tiles listed in
+// med.ztiles (a tile is P columns of one y; listed when one of its voxels is
+// not vacuum), the constitutive step scales by vs = 1 / n3 instead of 1 / n
+// (the forward x pass applies 1 / (n1 n2)), and a column left out keeps its
+// input, which is what the inverse z, identity, forward z sequence scaled by
+// 1 / n3 returns there.  The partial sums then hold Re f^* (M - I) f / n; the
+// first CG pass adds |p|^2 = sum |f|^2 / n.
 template <int N1, int N2, bool BT = false, bool PQ = false>
 __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView med,
                                                  double2* __restrict__ fld, int P, const int* skip,
-                                                 const InstDesc* __restrict__ insts, double* part_mid) {
+                                                 const InstDesc* __restrict__ insts, double* part_mid, double vs) {
   if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
@@ -238,13 +245,17 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
   if (skip && *skip) return;
   constexpr int N = N1 * N2;
   constexpr int D = Split<N1, N2>::D;
+  const int groups1 = g.n1 / P;
+  const unsigned tiles = vs > 0.0 ? (unsigned)med.nztiles : (unsigned)groups1 * (unsigned)g.n2;
+  if (blockIdx.x >= 3u * tiles) {  // batched: this instance has fewer listed tiles
+    if (PQ && threadIdx.x == 0) part_mid[blockIdx.x] = 0.0;
+    return;
+  }
   extern __shared__ double2 sm[];
   double2* twl = sm;
   double2* tile = sm + N;  // [(h * N + e) * P + p], h = 0 (E field), 1 (H field)
   const int twoff = g.n1 + g.n2;
   for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = t.tw[twoff + i];
-  const int groups1 = g.n1 / P;
-  const unsigned tiles = (unsigned)groups1 * (unsigned)g.n2;
   unsigned tix, q;
   if ((tiles & 7u) == 0) {
     const unsigned sq = blockIdx.x >> 3;
@@ -254,6 +265,7 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
     q = blockIdx.x % 3u;
     tix = blockIdx.x / 3u;
   }
+  if (vs > 0.0) tix = (unsigned)med.ztiles[tix];
   int fe, fh;
   bool coupled = true;
   if (med.kind == kMedChiral) {
@@ -324,7 +336,9 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
   }
   __syncthreads();
   const double inv_n = 1.0 / (double)n;
-  double pq[1] = {0.0};  // Re f^* (M f) / n: this thread's share of p^* A_r p
+  const double zs = vs > 0.0 ? vs : inv_n;  // scale of the constitutive step
+  const double pq_s = inv_n / zs;
+  double pq[1] = {0.0};  // Re f^* (M f) / n (vs > 0: Re f^* (M - I) f / n): this thread's share of p^* A_r p
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const int k1 = n2 + d * N2;
@@ -334,12 +348,15 @@ __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView me
         const int z = k1 + N1 * k2;
         const double2 m = mv[d][k2];
         const double eps = m.x, gm = coupled ? m.y : 0.0;
-        const double sc = inv_n / (eps - gm * gm);
+        const double sc = zs / (eps - gm * gm);
         const double2 other = Tq[z * P];
         const double2 own = out[d][k2];
         out[d][k2] = (h == 0) ? cscale(csub(cscale(own, eps), cmuli(cscale(other, gm))), sc)
                               : cscale(cadd(cmuli(cscale(other, gm)), own), sc);
-        if (PQ) pq[0] += own.x * out[d][k2].x + own.y * out[d][k2].y;
+        if (PQ) {
+          pq[0] += (own.x * out[d][k2].x + own.y * out[d][k2].y) * pq_s;
+          if (vs > 0.0) pq[0] -= cabs2(own) * inv_n;
+        }
       }
     }
   }
@@ -424,6 +441,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   const long long row0 = (long long)blockIdx.x * R;
   const long long n = g.n;
   double rr_acc[1] = {0.0};
+  double pn_acc[1] = {0.0};  // |p|^2 of this workgroup's frequencies (cg.pnorm, q-free)
   int cg_iter = 0;
   double cg_al = 0, cg_be = 0;
   // p of the previous iteration is read from pin and the new p written to
@@ -472,6 +490,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
           if (!ring) st_stream(cg.x + o, make_double2(xo[b].x + cg_al * po[b].x, xo[b].y + cg_al * po[b].y));
           st_stream(pout + o, pn);
           yv[b] = pn;
+          pn_acc[0] += cabs2(pn);
         }
       } else if (cg_iter > 0) {
 #pragma unroll
@@ -494,7 +513,10 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
         }
       } else {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) yv[b] = po[b];
+        for (int b = 0; b < 4; ++b) {
+          yv[b] = po[b];
+          pn_acc[0] += cabs2(po[b]);
+        }
       }
     }
     Basis B;
@@ -572,6 +594,10 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
 #pragma unroll
         for (int b = 0; b < 4; ++b) yv[b] = a0[it][b];
       }
+      if (CG) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pn_acc[0] += cabs2(yv[b]);
+      }
       Basis B;
       basis_at(t.lam, g, i1, i2, i3, B);
 #pragma unroll
@@ -593,6 +619,9 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
   if (CG && !QF) {
     block_sum_k<1>(rr_acc);
     if (threadIdx.x == 0) cg.part_in[blockIdx.x] = rr_acc[0];
+  } else if (CG && cg.pnorm) {
+    block_sum_k<1>(pn_acc);
+    if (threadIdx.x == 0) cg.part_in[blockIdx.x] = pn_acc[0];
   }
   __syncthreads();
   const int n2 = threadIdx.x % N2;
@@ -631,11 +660,12 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
 // NOPQ (with CG): the q-free schedule; r = r - alpha q in place of q, with
 // alpha = rr / pap from the CG state (0 when pap is not positive: the step
 // kernel then stops the solve with a breakdown).
+// ps scales the projected result (1 / (n1 n2) after a vacuum-skipping z pass, else 1).
 template <int N1, int N2, int PART, bool CG = false, bool BT = false, bool NOPQ = false>
 __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
                                                      double2* __restrict__ out, int R,
                                                      const int* skip, CgFuse cg,
-                                                     const InstDesc* __restrict__ insts) {
+                                                     const InstDesc* __restrict__ insts, double ps) {
   if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
@@ -734,6 +764,8 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
         oa = csub(oa, cmul(B.pi2[cc], o));
         ob = cadd(ob, cmul(B.pi1[cc], o));
       }
+      oa = cscale(oa, ps);
+      ob = cscale(ob, ps);
       if (!QF) {
         out[f] = oa;
         out[n + f] = ob;
@@ -749,6 +781,8 @@ __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const dou
         oc = cadd(oc, cmulc(B.pi1[cc], o));
         od = cadd(od, cmulc(B.pi2[cc], o));
       }
+      oc = cscale(oc, ps);
+      od = cscale(od, ps);
       if (!QF) {
         out[o0 + f] = oc;
         out[o0 + n + f] = od;
@@ -881,31 +915,38 @@ hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int
   return hipGetLastError();
 }
 
-int fast_z_mid_pq_items(const Geom& g, int medium_kind, int P_want) {
+int fast_z_pair_cols(const Geom& g, int medium_kind, int P_want) {
   const int N = g.n3;
   FastCfg cfg;
   if (!fast_cfg(N, cfg) || !g.mid_pairs || six_coupled(medium_kind)) return 0;
-  const size_t lmax = lds_limit() - 1024;
+  const size_t lmax = lds_limit() - 1024;  // room for the kernel's static LDS (reductions)
   int P = pick_cols(g.n1, P_want);
   while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax)) P /= 2;
   if (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax) return 0;
+  return P;
+}
+
+int fast_z_mid_pq_items(const Geom& g, int medium_kind, int P_want) {
+  const int P = fast_z_pair_cols(g, medium_kind, P_want);
+  if (!P) return 0;
   const unsigned items = (unsigned)(3 * (g.n1 / P) * g.n2);
   return items <= 2u * kMidSlots ? (int)items : 0;
 }
 
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
                              int P_want, const int* skip, hipStream_t s, const InstDesc* insts,
-                             int ninst, double* part_mid, int* np_mid) {
+                             int ninst, double* part_mid, int* np_mid, double vac_scale, int vac_tiles) {
   const int N = g.n3;
   if (np_mid) *np_mid = 0;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
   if (g.mid_pairs && !six_coupled(med.kind)) {  // general media couple all six fields
-    const size_t lmax = lds_limit() - 1024;  // room for the kernel's static LDS (reductions)
-    int P = pick_cols(g.n1, P_want);
-    while (P > 1 && (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax)) P /= 2;
-    if (2 * P * cfg.N2 > 256 || (size_t)(N + 2 * N * P) * 16 > lmax) return hipErrorInvalidValue;
-    const unsigned items = (unsigned)(3 * (g.n1 / P) * g.n2);
+    const int P = fast_z_pair_cols(g, med.kind, P_want);
+    if (!P) return hipErrorInvalidValue;
+    const bool vac = vac_scale > 0.0;
+    if (vac && vac_tiles < 0) return hipErrorInvalidValue;
+    const unsigned items = (unsigned)(3 * (vac ? vac_tiles : (g.n1 / P) * g.n2));
+    if (items == 0) return hipSuccess;  // every listed column is vacuum: nothing to do
     const dim3 block(2 * P * cfg.N2);
     const size_t lds = sizeof(double2) * (size_t)(N + 2 * N * P);
     const dim3 grid(items, 1, (unsigned)ninst);
@@ -932,16 +973,16 @@ hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& m
   }                                                                                                  \
   if (insts && pq)                                                                                   \
     hipLaunchKernelGGL((k_fz_pair<A, B, true, true>), grid, block, lds, s, g, t, med, fld, P, skip,  \
-                       insts, part_mid);                                                             \
+                       insts, part_mid, vac_scale);                                                  \
   else if (insts)                                                                                    \
     hipLaunchKernelGGL((k_fz_pair<A, B, true>), grid, block, lds, s, g, t, med, fld, P, skip, insts, \
-                       part_mid);                                                                    \
+                       part_mid, vac_scale);                                                         \
   else if (pq)                                                                                       \
     hipLaunchKernelGGL((k_fz_pair<A, B, false, true>), grid, block, lds, s, g, t, med, fld, P, skip, \
-                       insts, part_mid);                                                             \
+                       insts, part_mid, vac_scale);                                                  \
   else                                                                                               \
     hipLaunchKernelGGL((k_fz_pair<A, B>), grid, block, lds, s, g, t, med, fld, P, skip, insts,       \
-                       part_mid);
+                       part_mid, vac_scale);
     NSF_FAST_SWITCH(N, L_PAIR)
 #undef L_PAIR
     return hipGetLastError();
@@ -1005,7 +1046,7 @@ hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, con
 }
 
 hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld, double2* out,
-                                  const int* skip, hipStream_t s, const InstDesc* insts, int ninst) {
+                                  const int* skip, hipStream_t s, const InstDesc* insts, int ninst, double pscale) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -1021,16 +1062,16 @@ hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, cons
 #define L_XF(A, B)                                                                                     \
   if (part == kPartBoth && insts)                                                                      \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, false, true>), grid, block, lds, s, g, t, fld,    \
-                       out, R, skip, none, insts);                                                     \
+                       out, R, skip, none, insts, pscale);                                                     \
   else if (part == kPartBoth)                                                                          \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth>), grid, block, lds, s, g, t, fld, out, R, skip,  \
-                       none, insts);                                                                   \
+                       none, insts, pscale);                                                                   \
   else if (part == kPartP)                                                                             \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartP>), grid, block, lds, s, g, t, fld, out, R, skip,     \
-                       none, insts);                                                                   \
+                       none, insts, pscale);                                                                   \
   else                                                                                                 \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartQ>), grid, block, lds, s, g, t, fld, out, R, skip,     \
-                       none, insts);
+                       none, insts, pscale);
   NSF_FAST_SWITCH(N, L_XF)
 #undef L_XF
   return hipGetLastError();
@@ -1076,7 +1117,7 @@ hipError_t launch_fast_cg_first(const Geom& g, const Tables& t, const CgFuse& cg
 
 hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
                                const int* skip, int* nparts, hipStream_t s, const InstDesc* insts,
-                               int ninst, bool pq_done) {
+                               int ninst, bool pq_done, double pscale) {
   const int N = g.n1;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
@@ -1090,16 +1131,16 @@ hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg,
 #define L_CGL(A, B)                                                                                  \
   if (insts && pq_done)                                                                              \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, true, true>), grid, block, lds, s, g, t,  \
-                       fld, cg.q, R, skip, cg, insts);                                               \
+                       fld, cg.q, R, skip, cg, insts, pscale);                                               \
   else if (insts)                                                                                    \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, true>), grid, block, lds, s, g, t, fld,  \
-                       cg.q, R, skip, cg, insts);                                                    \
+                       cg.q, R, skip, cg, insts, pscale);                                                    \
   else if (pq_done)                                                                                  \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true, false, true>), grid, block, lds, s, g, t, \
-                       fld, cg.q, R, skip, cg, insts);                                               \
+                       fld, cg.q, R, skip, cg, insts, pscale);                                               \
   else                                                                                               \
     hipLaunchKernelGGL((k_fx_fwd_proj<A, B, kPartBoth, true>), grid, block, lds, s, g, t, fld, cg.q, \
-                       R, skip, cg, insts);
+                       R, skip, cg, insts, pscale);
   NSF_FAST_SWITCH(N, L_CGL)
 #undef L_CGL
   return hipGetLastError();

@@ -98,14 +98,40 @@ InstDesc desc_of(Run* r, bool cg) {
   return d;
 }
 
+// Whether the runs of G iterate in the q-free fused schedule.
+bool group_qfree(const Group& G) {
+  nsf_plan p0 = G.runs[0]->p;
+  if (G.fast) return fast_z_mid_pq_items(p0->geom, p0->medium_kind, p0->opt_mid_cols) > 0;
+  return cg_qfree(p0);
+}
+
+// Vacuum skipping for a group's shared launches: on when every run's plan has
+// it (same shape and tiling in a group); *zmax receives the most listed tiles.
+bool group_vac(const Group& G, int* zmax, double* zscale, double* pscale) {
+  int mx = 0;
+  for (Run* r : G.act) {
+    const VacSkip v = vac_of(r->p);
+    if (!v.on) return false;
+    mx = std::max(mx, v.ntiles);
+    *zscale = v.zscale;
+    *pscale = v.pscale;
+  }
+  *zmax = mx;
+  return !G.act.empty();
+}
+
 int upload_descs(Group& G, hipStream_t s) {
   G.act.clear();
   for (Run* r : G.runs)
     if (!r->finished) G.act.push_back(r);
   const int na = (int)G.act.size();
   if (!G.fast || na == 0) return NSF_OK;
+  int zmax = 0;
+  double zs = 0.0, ps = 1.0;
+  const bool vac = group_qfree(G) && group_vac(G, &zmax, &zs, &ps);
   for (int i = 0; i < na; ++i) {
     G.h_desc[i] = desc_of(G.act[i], true);
+    G.h_desc[i].cg.pnorm = vac ? 1 : 0;
     G.h_desc[na + i] = desc_of(G.act[i], false);
   }
   const hipError_t e = hipMemcpyAsync(G.d_desc, G.h_desc, sizeof(InstDesc) * 2 * na, hipMemcpyHostToDevice, s);
@@ -127,24 +153,21 @@ int apply_all(std::vector<Group>& groups, hipStream_t s) {
     nsf_plan p0 = G.act[0]->p;
     const Geom& g = p0->geom;
     const InstDesc* d = G.d_desc + na;
+    int zmax = -1;
+    double zs = 0.0, ps = 1.0;
+    if (!group_vac(G, &zmax, &zs, &ps)) zs = 0.0, ps = 1.0, zmax = -1;
     NSF_HIP(p0, launch_fast_x_inv_synth(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na,
+                                  nullptr, nullptr, zs, zmax));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_x_fwd_proj(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_x_fwd_proj(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na, ps));
   }
   return NSF_OK;
 }
 
 // One CG iteration of every unfinished run, enqueued on each run's plan stream
 // (single instances) or on s (groups sharing launches).
-// Whether the runs of G iterate in the q-free fused schedule.
-bool group_qfree(const Group& G) {
-  nsf_plan p0 = G.runs[0]->p;
-  if (G.fast) return fast_z_mid_pq_items(p0->geom, p0->medium_kind, p0->opt_mid_cols) > 0;
-  return cg_qfree(p0);
-}
-
 int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
   for (Group& G : groups) {
     const int na = (int)G.act.size();
@@ -161,17 +184,22 @@ int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
     const InstDesc* d = G.d_desc;
     const CgFuse none{};
     const bool qf = group_qfree(G);
+    int zmax = -1;
+    double zs = 0.0, ps = 1.0;
+    const bool vac = qf && group_vac(G, &zmax, &zs, &ps);  // the descriptors carry cg.pnorm = vac
+    if (!vac) zs = 0.0, ps = 1.0, zmax = -1;
     int np1 = 0, np5 = 0, npm = 0;
     NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na, qf));
     if (!qf) NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
     NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na,
-                                  nullptr, &npm));
-    if ((npm > 0) != qf) return set_error(p0, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
-    if (qf) NSF_HIP(p0, launch_cgf_alpha(nullptr, npm, nullptr, s, d, na));
+                                  nullptr, &npm, zs, zmax));
+    if (!vac && (npm > 0) != qf)
+      return set_error(p0, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
+    if (qf) NSF_HIP(p0, launch_cgf_alpha(nullptr, npm, nullptr, s, d, na, nullptr, vac ? np1 : 0));
     if (qf) NSF_HIP(p0, launch_cg_fold(nullptr, nullptr, 4 * g.n, nullptr, false, s, d, na));
     NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, qf));
+    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, qf, ps));
     if (qf)
       NSF_HIP(p0, launch_cgf_step_qf(nullptr, np5, nullptr, s, d, na));
     else

@@ -87,6 +87,11 @@ struct MediumView {
   const double2* mg;     // general media: kGenEntries per voxel (or per palette entry)
   const double2* mf;     // NFSEP media: kFullEntries per voxel (or per palette entry)
   const unsigned short* pidx;  // palette index per voxel, or null (factors stored per voxel)
+  // tiles of the field-pair z pass (P columns of one y, index x / P + (n1 / P) y)
+  // holding a voxel that is not vacuum, for the plan's current P; used only by
+  // a vacuum-skipping launch
+  const int* ztiles;
+  int nztiles;
 };
 
 // Which half of the synthesis / projection a pass performs.
@@ -141,13 +146,21 @@ hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int
 // partials of Re p^* A_r p (the fields' real-space quadratic form) to part_mid
 // (batched: to each descriptor's cg.part_mid) and sets *np_mid to their count;
 // otherwise *np_mid = 0.
+// vac_scale > 0 (vacuum skipping, field-pair kernel only): only the
+// med.ztiles tiles are transformed (vac_tiles workgroup triples: the listed
+// count, or the largest over a batch), scaled by vac_scale = 1 / n3; the
+// partials hold Re f^* (M - I) f / n.  The forward x pass must then scale by
+// 1 / (n1 n2) (pscale).
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
                              int P_want, const int* skip, hipStream_t s,
                              const struct InstDesc* insts = nullptr, int ninst = 1,
-                             double* part_mid = nullptr, int* np_mid = nullptr);
+                             double* part_mid = nullptr, int* np_mid = nullptr, double vac_scale = 0.0,
+                             int vac_tiles = -1);
+// Pencil columns per workgroup of the field-pair z pass (0: that kernel is not used).
+int fast_z_pair_cols(const Geom& g, int medium_kind, int P_want);
 hipError_t launch_fast_x_fwd_proj(const Geom& g, const Tables& t, int part, const double2* fld,
                                   double2* out, const int* skip, hipStream_t s,
-                                  const struct InstDesc* insts = nullptr, int ninst = 1);
+                                  const struct InstDesc* insts = nullptr, int ninst = 1, double pscale = 1.0);
 
 // Single-wave passes holding E' / H' components per lane (axis lengths 16,
 // 32, 64, 128); same semantics again.
@@ -202,6 +215,7 @@ struct CgFuse {
   double* part_in;   // per-workgroup |r|^2 of the first pass
   double* part_out;  // per-workgroup (Re p^*q, |q|^2, Re r^*q) of the last pass
   double* part_mid;  // per-workgroup Re p^* A_r p of the fused z pass (field pairs)
+  int pnorm;         // q-free: the first pass writes per-workgroup |p|^2 to part_in (vacuum skipping)
 };
 
 // Per-instance pointers of a batched launch (instances of one grid shape):
@@ -244,7 +258,8 @@ bool cg_qfree(nsf_plan p);
 // |r|^2.
 hipError_t launch_fast_cg_last(const Geom& g, const Tables& t, const CgFuse& cg, const double2* fld,
                                const int* skip, int* nparts, hipStream_t s,
-                               const InstDesc* insts = nullptr, int ninst = 1, bool pq_done = false);
+                               const InstDesc* insts = nullptr, int ninst = 1, bool pq_done = false,
+                               double pscale = 1.0);
 // Scalar steps of the fused CG: check |r|^2 after the first pass, then alpha,
 // beta from the last pass (|r - alpha q|^2 by expansion).
 // Batched forms (insts != nullptr): one workgroup per instance, partials and
@@ -259,8 +274,10 @@ hipError_t launch_cgf_step(const double* part_out, int nparts, CgState* st, hipS
 // the convergence test, iter + 1.  launch_cg_finish then applies the pending
 // x = x + alpha p of the final iteration once the state is done (not after a
 // breakdown).
+// With np_in > 0 (vacuum skipping) pap also adds the first pass's |p|^2 partials.
 hipError_t launch_cgf_alpha(const double* part_mid, int np_mid, CgState* st, hipStream_t s,
-                            const InstDesc* insts = nullptr, int ninst = 1);
+                            const InstDesc* insts = nullptr, int ninst = 1, const double* part_in = nullptr,
+                            int np_in = 0);
 hipError_t launch_cgf_step_qf(const double* part_out, int nparts, CgState* st, hipStream_t s,
                               const InstDesc* insts = nullptr, int ninst = 1);
 hipError_t launch_cg_finish(double2* x, const double2* p, long long len, const CgState* st, hipStream_t s);
@@ -401,6 +418,14 @@ struct nsf_plan_s {
   int opt_warm_chain = 0;   // nsf_batch_eigs: start from the previous instance's Ritz vectors
   int opt_cg_ring = 1;      // q-free CG keeps kCgRing directions instead of updating x
   double2* d_ring = nullptr;  // those directions, kCgRing x 4n
+  int opt_vacuum = 1;       // the field-pair z pass leaves out columns of vacuum
+
+  // z-pass tiles that are not all vacuum (chiral and pseudochiral media), one
+  // list per P = 1, 2, 4, 8, 16 columns per tile, built when the medium is set
+  int* d_ztiles = nullptr;
+  int ztile_off[5] = {0, 0, 0, 0, 0};
+  int ztile_cnt[5] = {-1, -1, -1, -1, -1};
+  size_t ztile_cap = 0;     // ints allocated at d_ztiles
 
   std::string last_error;
 };
@@ -433,9 +458,20 @@ int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip);
 hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, const int* skip);
 hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post_twist, int pre_twist,
                    const int* skip);
+// Vacuum skipping of the plan's A_r passes (opt_vacuum, a chiral or
+// pseudochiral medium, every axis on the two-level passes, the field-pair z
+// pass): on, with the z-pass scale 1 / n3, the forward x scale 1 / (n1 n2) and
+// the number of listed tiles.
+struct VacSkip {
+  bool on = false;
+  double zscale = 0.0, pscale = 1.0;
+  int ntiles = -1;
+};
+VacSkip vac_of(nsf_plan p);
 hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid = nullptr,
-                      int* np_mid = nullptr);
-hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip);
+                      int* np_mid = nullptr, const VacSkip* vac = nullptr);
+hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip,
+                      double pscale = 1.0);
 // cgv: the three CG vectors r, p, q (4n each, consecutive); nullptr: the plan's own.
 int cg_solve_dev(nsf_plan p, const double2* b, double2* x, double rtol, int maxit, int* iters,
                  double* relres, long long* matvecs, double2* cgv = nullptr);

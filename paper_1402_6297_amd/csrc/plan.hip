@@ -139,7 +139,32 @@ MediumView medium_view(nsf_plan p) {
   m.mg = p->d_mgen;
   m.mf = p->d_mfull;
   m.pidx = p->palette > 0 ? p->d_pidx : nullptr;
+  m.ztiles = nullptr;
+  m.nztiles = 0;
+  if ((m.kind == kMedChiral || m.kind == kMedPseudo) && p->d_ztiles) {
+    const int P = fast_z_pair_cols(p->geom, m.kind, p->opt_mid_cols);
+    int k = 0;
+    while (k < 5 && (1 << k) != P) ++k;
+    if (P > 0 && k < 5 && p->ztile_cnt[k] >= 0) {
+      m.ztiles = p->d_ztiles + p->ztile_off[k];
+      m.nztiles = p->ztile_cnt[k];
+    }
+  }
   return m;
+}
+
+VacSkip vac_of(nsf_plan p) {
+  VacSkip v;
+  const Geom& g = p->geom;
+  if (!p->opt_vacuum || p->opt_fft_path != 0 || !fast_axis(g.n1) || !fast_axis(g.n2) || !fast_axis(g.n3))
+    return v;
+  const MediumView m = medium_view(p);
+  if (!m.ztiles) return v;
+  v.on = true;
+  v.zscale = 1.0 / (double)g.n3;
+  v.pscale = 1.0 / ((double)g.n1 * (double)g.n2);
+  v.ntiles = m.nztiles;
+  return v;
 }
 
 hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, const int* skip) {
@@ -166,9 +191,13 @@ int z_mid_pq_items(nsf_plan p) {
   return 0;
 }
 
-hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid, int* np_mid) {
+hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid, int* np_mid,
+                      const VacSkip* vac) {
   const Geom& g = p->geom;
   if (np_mid) *np_mid = 0;
+  if (vac && vac->on)  // (vac_of chose the field-pair kernel of the two-level passes)
+    return launch_fast_z_mid(g, p->tabs, medium_view(p), fld, p->opt_mid_cols, skip, p->stream, nullptr, 1,
+                             part_mid, np_mid, vac->zscale, vac->ntiles);
   if (p->opt_fft_path == 2 && wave_mid_ok(g) && !six_coupled(p->medium_kind))
     return launch_wave_z_mid(g, p->tabs, medium_view(p), fld, skip, p->stream);
   if (p->opt_fft_path != 1 && fast_axis(g.n3))
@@ -177,8 +206,10 @@ hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mi
   return launch_z_mid(g, p->ax[2], p->tabs, medium_view(p), fld, skip, p->stream);
 }
 
-hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip) {
+hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip, double pscale) {
   const Geom& g = p->geom;
+  if (pscale != 1.0)  // after a vacuum-skipping z pass (two-level passes only)
+    return launch_fast_x_fwd_proj(g, p->tabs, part, fld, out, skip, p->stream, nullptr, 1, pscale);
   if (p->opt_fft_path == 2 && wave_axis(g.n1) && g.n <= (1LL << 32) / 96)
     return launch_wave_x_fwd_proj(g, p->tabs, part, fld, out, skip, p->stream);
   if (p->opt_fft_path != 1 && fast_axis(g.n1))
@@ -190,11 +221,12 @@ hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, co
 // [inverse z, middle factor, forward z] [forward y] [forward x + projection].
 int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip) {
   double2* F = p->d_fields;
+  const VacSkip v = vac_of(p);
   NSF_HIP(p, pass_x_inv(p, kPartBoth, u, F, skip));
   NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, skip));
-  NSF_HIP(p, pass_z_mid(p, F, skip));
+  NSF_HIP(p, pass_z_mid(p, F, skip, nullptr, nullptr, &v));
   NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, skip));
-  NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, skip));
+  NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, skip, v.on ? v.pscale : 1.0));
   return NSF_OK;
 }
 
@@ -356,6 +388,7 @@ void nsf_plan_destroy(nsf_plan p) {
     if (p->d_pidx) hipFree(p->d_pidx);
     if (p->d_cg && !p->ws) hipFree(p->d_cg);
     if (p->d_ring) hipFree(p->d_ring);
+    if (p->d_ztiles) hipFree(p->d_ztiles);
     if (p->d_basis && !p->ws) hipFree(p->d_basis);
     if (p->d_small && !p->ws) hipFree(p->d_small);
   }
@@ -459,6 +492,10 @@ int nsf_plan_set_option(nsf_plan p, int option, int value) {
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_RING takes 0 or 1");
       p->opt_cg_ring = value;
       return NSF_OK;
+    case NSF_OPT_VACUUM:
+      if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_VACUUM takes 0 or 1");
+      p->opt_vacuum = value;
+      return NSF_OK;
     case NSF_OPT_CG_GRAPH:
       if (value < 0 || value > 1) return set_error(p, NSF_E_ARG, "NSF_OPT_CG_GRAPH takes 0 or 1");
       p->opt_cg_graph = value;
@@ -533,6 +570,44 @@ int set_medium(nsf_plan p, int kind, int pa, int pb, const double* eps, const do
   if (!p->d_medium) NSF_HIP(p, hipMalloc(&p->d_medium, sizeof(double2) * n));
   NSF_HIP(p, hipMemcpyAsync(p->d_medium, packed.data(), sizeof(double2) * n, hipMemcpyHostToDevice,
                             p->stream));
+  // Tiles of the field-pair z pass (P columns x .. x + P - 1 of one y) that hold
+  // a voxel other than vacuum (eps 1, gamma 0), for P = 1, 2, 4, 8, 16; a
+  // vacuum-skipping apply transforms only these.
+  {
+    const int n1 = p->geom.n1, n2 = p->geom.n2, n3 = p->geom.n3;
+    std::vector<unsigned char> col((size_t)n1 * n2, 0);
+    for (long long z = 0; z < n3; ++z)
+      for (long long yx = 0; yx < (long long)n1 * n2; ++yx) {
+        const long long v = z * n1 * n2 + yx;
+        if (e[v] != 1.0 || c[v] != 0.0) col[yx] = 1;
+      }
+    std::vector<int> list;
+    for (int k = 0; k < 5; ++k) {
+      const int P = 1 << k;
+      p->ztile_off[k] = (int)list.size();
+      p->ztile_cnt[k] = -1;
+      if (n1 % P) continue;
+      const int groups = n1 / P;
+      for (int y = 0; y < n2; ++y)
+        for (int gx = 0; gx < groups; ++gx) {
+          bool any = false;
+          for (int j = 0; j < P && !any; ++j) any = col[(size_t)y * n1 + gx * P + j] != 0;
+          if (any) list.push_back(gx + groups * y);
+        }
+      p->ztile_cnt[k] = (int)list.size() - p->ztile_off[k];
+    }
+    const size_t need = std::max<size_t>(list.size(), 1);
+    if (need > p->ztile_cap) {
+      if (p->d_ztiles) NSF_HIP(p, hipFree(p->d_ztiles));
+      p->d_ztiles = nullptr;
+      p->ztile_cap = 0;
+      NSF_HIP(p, hipMalloc(&p->d_ztiles, sizeof(int) * need));
+      p->ztile_cap = need;
+    }
+    if (!list.empty())
+      NSF_HIP(p, hipMemcpyAsync(p->d_ztiles, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice,
+                                p->stream));
+  }
   NSF_HIP(p, hipStreamSynchronize(p->stream));
   p->medium_kind = kind;
   p->pa = pa;
@@ -910,17 +985,18 @@ int nsf_profile_Ar(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n, int reps, d
   hipEvent_t ev[kPasses + 1];
   for (auto& e : ev) NSF_HIP(p, hipEventCreate(&e));
   double acc[kPasses] = {0, 0, 0, 0, 0};
+  const VacSkip v = vac_of(p);
   for (int r = 0; r < reps; ++r) {
     NSF_HIP(p, hipEventRecord(ev[0], s));
     NSF_HIP(p, pass_x_inv(p, kPartBoth, u, F, nullptr));
     NSF_HIP(p, hipEventRecord(ev[1], s));
     NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, nullptr));
     NSF_HIP(p, hipEventRecord(ev[2], s));
-    NSF_HIP(p, pass_z_mid(p, F, nullptr));
+    NSF_HIP(p, pass_z_mid(p, F, nullptr, nullptr, nullptr, &v));
     NSF_HIP(p, hipEventRecord(ev[3], s));
     NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, nullptr));
     NSF_HIP(p, hipEventRecord(ev[4], s));
-    NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, nullptr));
+    NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, nullptr, v.on ? v.pscale : 1.0));
     NSF_HIP(p, hipEventRecord(ev[5], s));
     NSF_HIP(p, hipEventSynchronize(ev[5]));
     for (int i = 0; i < kPasses; ++i) {

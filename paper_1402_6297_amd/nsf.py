@@ -46,6 +46,7 @@ NSF_OPT_MEDIUM_PALETTE = 11
 NSF_OPT_CG_RELAX = 12
 NSF_OPT_WARM_CHAIN = 13
 NSF_OPT_CG_RING = 14
+NSF_OPT_VACUUM = 15
 
 EXPORTED = [
     "nsf_plan_create", "nsf_plan_destroy", "nsf_plan_query", "nsf_plan_set_option",

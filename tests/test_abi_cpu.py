@@ -135,6 +135,7 @@ def test_status_strings():
     (nsf.NSF_OPT_CG_RELAX, [0, 1], [-1, 2]),
     (nsf.NSF_OPT_WARM_CHAIN, [0, 1], [-1, 2]),
     (nsf.NSF_OPT_CG_RING, [0, 1], [-1, 2]),
+    (nsf.NSF_OPT_VACUUM, [0, 1], [-1, 2]),
     (nsf.NSF_OPT_MEDIUM_PALETTE, [0, 1], [-1, 2]),
 ])
 def test_plan_options_validate(option, good, bad):
