@@ -183,15 +183,15 @@ enum {
                             on the two-level passes, the field-pair z pass
                             transforms only the tiles (P pencil columns of
                             one y) holding a voxel other than vacuum (eps 1,
-                            gamma 0): in a vacuum column the middle factor
-                            is the identity, so inverse z, middle factor and
-                            forward z return the column unchanged once the
-                            1/n normalisation is split as 1/n3 in that pass
-                            and 1/(n1 n2) in the projection.  p^* A_r p is
-                            then |p|^2 plus the listed columns' share.  The
-                            lists are built when the medium is set.  Same
-                            operator up to rounding; 0 transforms every
-                            column                                          */
+                            gamma 0), and both y passes only the groups of
+                            consecutive x holding one: where the middle
+                            factor is the identity the transforms around it
+                            cancel, once the 1/n normalisation is split as
+                            1/n3 (z pass), 1/n2 (forward y) and 1/n1
+                            (projection).  p^* A_r p is then |p|^2 plus the
+                            listed tiles' share.  The lists are built when
+                            the medium is set.  Same operator up to
+                            rounding; 0 transforms everything              */
 };
 
 /*

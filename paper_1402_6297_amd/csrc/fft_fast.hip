@@ -40,17 +40,29 @@ struct Split {
 // ------------------------------------------------------------ y / z passes
 // P pencils (consecutive x) per workgroup, N2 threads per pencil, lane order
 // p fastest.  LDS tile[(e) * P + p], e = n2 + N2 k1.
+// ysc > 0 (vacuum skipping, y axis): the grid covers nxg groups of P x columns
+// per z, taken from the list xg (batched: each instance's med.xgroups, nxg the
+// largest count); the results are scaled by ysc.  A group left out has no
+// voxel other than vacuum, so the y transforms around the z pass cancel there.
 template <int N1, int N2, int S, bool BT = false>
 __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2* __restrict__ fld,
                                              int P, int post_twist, int pre_twist, const int* skip,
-                                             const InstDesc* __restrict__ insts) {
+                                             const InstDesc* __restrict__ insts, const int* xg, int nxg,
+                                             double ysc) {
+  int mine = nxg;
   if constexpr (BT) {
     const InstDesc& d = insts[blockIdx.z];
     t = d.t;
     fld = d.fld;
     skip = d.skip;
+    xg = d.med.xgroups;
+    mine = d.med.nxgroups;
   }
   if (skip && *skip) return;
+  const int groups1 = g.n1 / P;
+  const int ng = ysc > 0.0 ? nxg : groups1;
+  const int gsel = (int)(blockIdx.x % (unsigned)ng);
+  if (ysc > 0.0 && gsel >= mine) return;  // batched: this instance lists fewer groups
   constexpr int N = N1 * N2;
   constexpr int D = Split<N1, N2>::D;
   extern __shared__ double2 sm[];
@@ -60,9 +72,8 @@ __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2
   for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = t.tw[twoff + i];
   const int p = threadIdx.x % P;
   const int n2 = threadIdx.x / P;
-  const int groups1 = g.n1 / P;
-  const int i1_0 = (int)(blockIdx.x % groups1) * P;
-  const int io = (int)(blockIdx.x / groups1);
+  const int i1_0 = (ysc > 0.0 ? xg[gsel] : gsel) * P;
+  const int io = (int)(blockIdx.x / (unsigned)ng);
   long long base, stride;
   if (axis == 1) {
     base = (long long)io * g.n1 * g.n2 + i1_0;
@@ -99,6 +110,7 @@ __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2
         const int j = k1 + N1 * k2;
         double2 x = u[k2];
         if (post_twist) x = cscale(cmul(twist_at(t.twist, g, i1_0 + p, io, j), x), rs);
+        if (ysc > 0.0) x = cscale(x, ysc);
         F[j * stride] = x;
       }
     }
@@ -886,30 +898,39 @@ bool fast_axis(int N) {
   return fast_cfg(N, c);
 }
 
+int fast_yz_cols(const Geom& g, int axis) {
+  FastCfg cfg;
+  if (!fast_cfg(axis == 1 ? g.n2 : g.n3, cfg)) return 0;
+  return pick_cols(g.n1, std::min(std::min(256 / cfg.N2, 16), std::max(g.yz_cols, 1)));
+}
+
 hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int nf, double2* fld,
                           int post_twist, int pre_twist, const int* skip, hipStream_t s,
-                          const InstDesc* insts, int ninst) {
+                          const InstDesc* insts, int ninst, const int* xg, int nxg, double ysc) {
   const int N = axis == 1 ? g.n2 : g.n3;
   FastCfg cfg;
   if (!fast_cfg(N, cfg)) return hipErrorInvalidValue;
-  const int P = pick_cols(g.n1, std::min(std::min(256 / cfg.N2, 16), std::max(g.yz_cols, 1)));
+  const int P = fast_yz_cols(g, axis);
   const long long other = (axis == 1) ? g.n3 : g.n2;
-  const dim3 grid((unsigned)((g.n1 / P) * other), (unsigned)nf, (unsigned)ninst);
+  if (ysc > 0.0 && (axis != 1 || nxg < 0 || (!insts && !xg))) return hipErrorInvalidValue;
+  if (ysc > 0.0 && nxg == 0) return hipSuccess;  // every x group is vacuum
+  const long long groups = ysc > 0.0 ? nxg : g.n1 / P;
+  const dim3 grid((unsigned)(groups * other), (unsigned)nf, (unsigned)ninst);
   const dim3 block(P * cfg.N2);
   const size_t lds = sizeof(double2) * (size_t)(N + N * P);
 #define L_YZ(A, B)                                                                                   \
   if (insts && dir > 0)                                                                              \
     hipLaunchKernelGGL((k_fyz<A, B, +1, true>), grid, block, lds, s, g, t, axis, fld, P, post_twist, \
-                       pre_twist, skip, insts);                                                      \
+                       pre_twist, skip, insts, xg, nxg, ysc);                                       \
   else if (insts)                                                                                    \
     hipLaunchKernelGGL((k_fyz<A, B, -1, true>), grid, block, lds, s, g, t, axis, fld, P, post_twist, \
-                       pre_twist, skip, insts);                                                      \
+                       pre_twist, skip, insts, xg, nxg, ysc);                                       \
   else if (dir > 0)                                                                                  \
     hipLaunchKernelGGL((k_fyz<A, B, +1>), grid, block, lds, s, g, t, axis, fld, P, post_twist,       \
-                       pre_twist, skip, insts);                                                      \
+                       pre_twist, skip, insts, xg, nxg, ysc);                                       \
   else                                                                                               \
     hipLaunchKernelGGL((k_fyz<A, B, -1>), grid, block, lds, s, g, t, axis, fld, P, post_twist,       \
-                       pre_twist, skip, insts);
+                       pre_twist, skip, insts, xg, nxg, ysc);
   NSF_FAST_SWITCH(N, L_YZ)
 #undef L_YZ
   return hipGetLastError();

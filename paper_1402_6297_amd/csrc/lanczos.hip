@@ -106,17 +106,19 @@ bool group_qfree(const Group& G) {
 }
 
 // Vacuum skipping for a group's shared launches: on when every run's plan has
-// it (same shape and tiling in a group); *zmax receives the most listed tiles.
-bool group_vac(const Group& G, int* zmax, double* zscale, double* pscale) {
-  int mx = 0;
+// it (same shape and tiling in a group), with the largest listed counts of
+// z tiles and y-pass x groups over the instances.
+bool group_vac(const Group& G, VacSkip* out) {
+  VacSkip acc;
   for (Run* r : G.act) {
     const VacSkip v = vac_of(r->p);
     if (!v.on) return false;
-    mx = std::max(mx, v.ntiles);
-    *zscale = v.zscale;
-    *pscale = v.pscale;
+    const int zt = std::max(acc.ntiles, v.ntiles), xg = std::max(acc.nxg, v.nxg);
+    acc = v;
+    acc.ntiles = zt;
+    acc.nxg = xg;
   }
-  *zmax = mx;
+  *out = acc;
   return !G.act.empty();
 }
 
@@ -126,9 +128,8 @@ int upload_descs(Group& G, hipStream_t s) {
     if (!r->finished) G.act.push_back(r);
   const int na = (int)G.act.size();
   if (!G.fast || na == 0) return NSF_OK;
-  int zmax = 0;
-  double zs = 0.0, ps = 1.0;
-  const bool vac = group_qfree(G) && group_vac(G, &zmax, &zs, &ps);
+  VacSkip gv;
+  const bool vac = group_qfree(G) && group_vac(G, &gv);
   for (int i = 0; i < na; ++i) {
     G.h_desc[i] = desc_of(G.act[i], true);
     G.h_desc[i].cg.pnorm = vac ? 1 : 0;
@@ -153,15 +154,16 @@ int apply_all(std::vector<Group>& groups, hipStream_t s) {
     nsf_plan p0 = G.act[0]->p;
     const Geom& g = p0->geom;
     const InstDesc* d = G.d_desc + na;
-    int zmax = -1;
-    double zs = 0.0, ps = 1.0;
-    if (!group_vac(G, &zmax, &zs, &ps)) zs = 0.0, ps = 1.0, zmax = -1;
+    VacSkip v;
+    if (!group_vac(G, &v)) v = VacSkip{};
     NSF_HIP(p0, launch_fast_x_inv_synth(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na, nullptr, v.nxg,
+                               v.on ? 1.0 : 0.0));
     NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na,
-                                  nullptr, nullptr, zs, zmax));
-    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_x_fwd_proj(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na, ps));
+                                  nullptr, nullptr, v.zscale, v.ntiles));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na, nullptr, v.nxg,
+                               v.on ? v.yscale : 0.0));
+    NSF_HIP(p0, launch_fast_x_fwd_proj(g, p0->tabs, kPartBoth, nullptr, nullptr, nullptr, s, d, na, v.pscale));
   }
   return NSF_OK;
 }
@@ -184,22 +186,23 @@ int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
     const InstDesc* d = G.d_desc;
     const CgFuse none{};
     const bool qf = group_qfree(G);
-    int zmax = -1;
-    double zs = 0.0, ps = 1.0;
-    const bool vac = qf && group_vac(G, &zmax, &zs, &ps);  // the descriptors carry cg.pnorm = vac
-    if (!vac) zs = 0.0, ps = 1.0, zmax = -1;
+    VacSkip v;
+    const bool vac = qf && group_vac(G, &v);  // the descriptors carry cg.pnorm = vac
+    if (!vac) v = VacSkip{};
     int np1 = 0, np5 = 0, npm = 0;
     NSF_HIP(p0, launch_fast_cg_first(g, p0->tabs, none, nullptr, nullptr, &np1, s, d, na, qf));
     if (!qf) NSF_HIP(p0, launch_cgf_check(nullptr, np1, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, +1, 6, nullptr, 0, 0, nullptr, s, d, na, nullptr, v.nxg,
+                               vac ? 1.0 : 0.0));
     NSF_HIP(p0, launch_fast_z_mid(g, p0->tabs, medium_view(p0), nullptr, p0->opt_mid_cols, nullptr, s, d, na,
-                                  nullptr, &npm, zs, zmax));
+                                  nullptr, &npm, v.zscale, v.ntiles));
     if (!vac && (npm > 0) != qf)
       return set_error(p0, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
     if (qf) NSF_HIP(p0, launch_cgf_alpha(nullptr, npm, nullptr, s, d, na, nullptr, vac ? np1 : 0));
     if (qf) NSF_HIP(p0, launch_cg_fold(nullptr, nullptr, 4 * g.n, nullptr, false, s, d, na));
-    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na));
-    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, qf, ps));
+    NSF_HIP(p0, launch_fast_yz(g, p0->tabs, 1, -1, 6, nullptr, 0, 0, nullptr, s, d, na, nullptr, v.nxg,
+                               vac ? v.yscale : 0.0));
+    NSF_HIP(p0, launch_fast_cg_last(g, p0->tabs, none, nullptr, nullptr, &np5, s, d, na, qf, v.pscale));
     if (qf)
       NSF_HIP(p0, launch_cgf_step_qf(nullptr, np5, nullptr, s, d, na));
     else

@@ -92,6 +92,10 @@ struct MediumView {
   // a vacuum-skipping launch
   const int* ztiles;
   int nztiles;
+  // groups of consecutive x (the y pass's pencils per workgroup, index x / P)
+  // holding a voxel that is not vacuum, for a vacuum-skipping y pass
+  const int* xgroups;
+  int nxgroups;
 };
 
 // Which half of the synthesis / projection a pass performs.
@@ -139,9 +143,15 @@ bool fast_axis(int N);
 hipError_t launch_fast_x_inv_synth(const Geom& g, const Tables& t, int part, const double2* y,
                                    double2* fld, const int* skip, hipStream_t s,
                                    const struct InstDesc* insts = nullptr, int ninst = 1);
+// ysc > 0 (vacuum skipping, axis 1 only): transform only the x groups listed in
+// xg (nxg of them; batched: each instance's med.xgroups, nxg the largest
+// count) and scale the results by ysc.
 hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int nf, double2* fld,
                           int post_twist, int pre_twist, const int* skip, hipStream_t s,
-                          const struct InstDesc* insts = nullptr, int ninst = 1);
+                          const struct InstDesc* insts = nullptr, int ninst = 1, const int* xg = nullptr,
+                          int nxg = -1, double ysc = 0.0);
+// Pencils (consecutive x) per workgroup of the two-level y (axis 1) or z pass.
+int fast_yz_cols(const Geom& g, int axis);
 // With np_mid given and the field-pair kernel in use, also writes per-workgroup
 // partials of Re p^* A_r p (the fields' real-space quadratic form) to part_mid
 // (batched: to each descriptor's cg.part_mid) and sets *np_mid to their count;
@@ -425,6 +435,8 @@ struct nsf_plan_s {
   int* d_ztiles = nullptr;
   int ztile_off[5] = {0, 0, 0, 0, 0};
   int ztile_cnt[5] = {-1, -1, -1, -1, -1};
+  int xgrp_off[5] = {0, 0, 0, 0, 0};    // x groups with a voxel other than vacuum, same buffer
+  int xgrp_cnt[5] = {-1, -1, -1, -1, -1};
   size_t ztile_cap = 0;     // ints allocated at d_ztiles
 
   std::string last_error;
@@ -454,20 +466,22 @@ void trace_solve(const char* call, nsf_plan p, int instance, int nev, int status
                  const double* resid);
 MediumView medium_view(nsf_plan p);
 int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip);
+// Vacuum skipping of the plan's A_r passes (opt_vacuum, a chiral or
+// pseudochiral medium, every axis on the two-level passes, the field-pair z
+// pass): the z pass transforms only the listed tiles, scaled by 1 / n3; both
+// y passes only the listed x groups, the forward one scaled by 1 / n2; the
+// projection scales by 1 / n1.
+struct VacSkip {
+  bool on = false;
+  double zscale = 0.0, pscale = 1.0, yscale = 0.0;
+  int ntiles = -1;  // listed z-pass tiles
+  int nxg = -1;     // listed y-pass x groups
+};
+VacSkip vac_of(nsf_plan p);
 // Pass dispatch (fast path when the axis allows it, else generic).
 hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, const int* skip);
 hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post_twist, int pre_twist,
-                   const int* skip);
-// Vacuum skipping of the plan's A_r passes (opt_vacuum, a chiral or
-// pseudochiral medium, every axis on the two-level passes, the field-pair z
-// pass): on, with the z-pass scale 1 / n3, the forward x scale 1 / (n1 n2) and
-// the number of listed tiles.
-struct VacSkip {
-  bool on = false;
-  double zscale = 0.0, pscale = 1.0;
-  int ntiles = -1;
-};
-VacSkip vac_of(nsf_plan p);
+                   const int* skip, const VacSkip* vac = nullptr);
 hipError_t pass_z_mid(nsf_plan p, double2* fld, const int* skip, double* part_mid = nullptr,
                       int* np_mid = nullptr, const VacSkip* vac = nullptr);
 hipError_t pass_x_fwd(nsf_plan p, int part, const double2* fld, double2* out, const int* skip,

@@ -141,13 +141,21 @@ MediumView medium_view(nsf_plan p) {
   m.pidx = p->palette > 0 ? p->d_pidx : nullptr;
   m.ztiles = nullptr;
   m.nztiles = 0;
+  m.xgroups = nullptr;
+  m.nxgroups = 0;
   if ((m.kind == kMedChiral || m.kind == kMedPseudo) && p->d_ztiles) {
-    const int P = fast_z_pair_cols(p->geom, m.kind, p->opt_mid_cols);
-    int k = 0;
-    while (k < 5 && (1 << k) != P) ++k;
-    if (P > 0 && k < 5 && p->ztile_cnt[k] >= 0) {
-      m.ztiles = p->d_ztiles + p->ztile_off[k];
-      m.nztiles = p->ztile_cnt[k];
+    auto log2_of = [](int P) {
+      int k = 0;
+      while (k < 5 && (1 << k) != P) ++k;
+      return P > 0 ? k : 5;
+    };
+    const int kz = log2_of(fast_z_pair_cols(p->geom, m.kind, p->opt_mid_cols));
+    const int ky = log2_of(fast_yz_cols(p->geom, 1));
+    if (kz < 5 && ky < 5 && p->ztile_cnt[kz] >= 0 && p->xgrp_cnt[ky] >= 0) {
+      m.ztiles = p->d_ztiles + p->ztile_off[kz];
+      m.nztiles = p->ztile_cnt[kz];
+      m.xgroups = p->d_ztiles + p->xgrp_off[ky];
+      m.nxgroups = p->xgrp_cnt[ky];
     }
   }
   return m;
@@ -162,8 +170,10 @@ VacSkip vac_of(nsf_plan p) {
   if (!m.ztiles) return v;
   v.on = true;
   v.zscale = 1.0 / (double)g.n3;
-  v.pscale = 1.0 / ((double)g.n1 * (double)g.n2);
+  v.yscale = 1.0 / (double)g.n2;
+  v.pscale = 1.0 / (double)g.n1;
   v.ntiles = m.nztiles;
+  v.nxg = m.nxgroups;
   return v;
 }
 
@@ -177,8 +187,11 @@ hipError_t pass_x_inv(nsf_plan p, int part, const double2* y, double2* fld, cons
 }
 
 hipError_t pass_yz(nsf_plan p, int axis, int dir, int nf, double2* fld, int post_twist, int pre_twist,
-                   const int* skip) {
+                   const int* skip, const VacSkip* vac) {
   const Geom& g = p->geom;
+  if (vac && vac->on && axis == 1)  // (vac_of chose the two-level passes)
+    return launch_fast_yz(g, p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream, nullptr, 1,
+                          medium_view(p).xgroups, vac->nxg, dir > 0 ? 1.0 : vac->yscale);
   if (p->opt_fft_path != 1 && fast_axis(axis == 1 ? g.n2 : g.n3))
     return launch_fast_yz(g, p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
   return launch_yz_pass(g, p->ax[axis], p->tabs, axis, dir, nf, fld, post_twist, pre_twist, skip, p->stream);
@@ -223,9 +236,9 @@ int apply_Ar_dev(nsf_plan p, const double2* u, double2* out, const int* skip) {
   double2* F = p->d_fields;
   const VacSkip v = vac_of(p);
   NSF_HIP(p, pass_x_inv(p, kPartBoth, u, F, skip));
-  NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, skip));
+  NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, skip, &v));
   NSF_HIP(p, pass_z_mid(p, F, skip, nullptr, nullptr, &v));
-  NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, skip));
+  NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, skip, &v));
   NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, skip, v.on ? v.pscale : 1.0));
   return NSF_OK;
 }
@@ -595,6 +608,23 @@ int set_medium(nsf_plan p, int kind, int pa, int pb, const double* eps, const do
           if (any) list.push_back(gx + groups * y);
         }
       p->ztile_cnt[k] = (int)list.size() - p->ztile_off[k];
+    }
+    // groups of P consecutive x (the y pass's pencils) holding such a voxel
+    std::vector<unsigned char> xact(n1, 0);
+    for (int y = 0; y < n2; ++y)
+      for (int x = 0; x < n1; ++x)
+        if (col[(size_t)y * n1 + x]) xact[x] = 1;
+    for (int k = 0; k < 5; ++k) {
+      const int P = 1 << k;
+      p->xgrp_off[k] = (int)list.size();
+      p->xgrp_cnt[k] = -1;
+      if (n1 % P) continue;
+      for (int gx = 0; gx < n1 / P; ++gx) {
+        bool any = false;
+        for (int j = 0; j < P && !any; ++j) any = xact[gx * P + j] != 0;
+        if (any) list.push_back(gx);
+      }
+      p->xgrp_cnt[k] = (int)list.size() - p->xgrp_off[k];
     }
     const size_t need = std::max<size_t>(list.size(), 1);
     if (need > p->ztile_cap) {
@@ -990,11 +1020,11 @@ int nsf_profile_Ar(nsf_plan p, const nsf_c128* u4n, nsf_c128* out4n, int reps, d
     NSF_HIP(p, hipEventRecord(ev[0], s));
     NSF_HIP(p, pass_x_inv(p, kPartBoth, u, F, nullptr));
     NSF_HIP(p, hipEventRecord(ev[1], s));
-    NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, nullptr));
+    NSF_HIP(p, pass_yz(p, 1, +1, 6, F, 0, 0, nullptr, &v));
     NSF_HIP(p, hipEventRecord(ev[2], s));
     NSF_HIP(p, pass_z_mid(p, F, nullptr, nullptr, nullptr, &v));
     NSF_HIP(p, hipEventRecord(ev[3], s));
-    NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, nullptr));
+    NSF_HIP(p, pass_yz(p, 1, -1, 6, F, 0, 0, nullptr, &v));
     NSF_HIP(p, hipEventRecord(ev[4], s));
     NSF_HIP(p, pass_x_fwd(p, kPartBoth, F, out, nullptr, v.on ? v.pscale : 1.0));
     NSF_HIP(p, hipEventRecord(ev[5], s));

@@ -165,14 +165,14 @@ int cg_iteration(nsf_plan p, double2* x, bool fused, double2* cgv) {
     int np1 = 0, np5 = 0;
     NSF_HIP(p, launch_fast_cg_first(p->geom, p->tabs, cgf, p->d_fields, skip, &np1, s, nullptr, 1, qf));
     if (!qf) NSF_HIP(p, launch_cgf_check(cgf.part_in, np1, st, s));
-    NSF_HIP(p, pass_yz(p, 1, +1, 6, p->d_fields, 0, 0, skip));
+    NSF_HIP(p, pass_yz(p, 1, +1, 6, p->d_fields, 0, 0, skip, &v));
     int npm = 0;
     NSF_HIP(p, pass_z_mid(p, p->d_fields, skip, cgf.part_mid, &npm, &v));
     if (!v.on && (npm > 0) != qf)
       return set_error(p, NSF_E_HIP, "fused CG: the z pass does not match the schedule");
     if (qf) NSF_HIP(p, launch_cgf_alpha(cgf.part_mid, npm, st, s, nullptr, 1, cgf.part_in, v.on ? np1 : 0));
     if (qf && cgf.ring) NSF_HIP(p, launch_cg_fold(x, cgf.ring, len, st, false, s));
-    NSF_HIP(p, pass_yz(p, 1, -1, 6, p->d_fields, 0, 0, skip));
+    NSF_HIP(p, pass_yz(p, 1, -1, 6, p->d_fields, 0, 0, skip, &v));
     NSF_HIP(p, launch_fast_cg_last(p->geom, p->tabs, cgf, p->d_fields, skip, &np5, s, nullptr, 1, qf,
                                    v.on ? v.pscale : 1.0));
     if (qf)

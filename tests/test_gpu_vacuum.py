@@ -1,7 +1,8 @@
-"""Vacuum skipping of the field-pair z pass (NSF_OPT_VACUUM = 1, the default).
+"""Vacuum skipping (NSF_OPT_VACUUM = 1, the default).
 
 In a pencil column where every voxel is vacuum (eps 1, gamma 0) the middle factor
-is the identity, so the z pass leaves such columns out.  Checked here: the apply
+is the identity, so the z pass leaves such columns out, and the y passes leave
+out groups of x with no other voxel.  Checked here: the apply
 with and without skipping on chiral and pseudochiral media at every z-pass
 tiling, against the oracle; air (every column skipped: A_r = I); a medium
 without vacuum; CG, eigensolves and a shared batch whose instances list
@@ -32,7 +33,7 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def _plan(grid, k, kind, eps, gam, vac, mid=None):
+def _plan(grid, k, kind, eps, gam, vac, mid=None, yz=None):
     P = nsf.Plan(grid, k)
     if kind == "chiral":
         P.set_chiral(eps, gam)
@@ -41,12 +42,14 @@ def _plan(grid, k, kind, eps, gam, vac, mid=None):
     P.set_option(nsf.NSF_OPT_VACUUM, vac)
     if mid:
         P.set_option(nsf.NSF_OPT_MID_COLS, mid)
+    if yz:
+        P.set_option(nsf.NSF_OPT_YZ_COLS, yz)
     return P
 
 
 @pytest.mark.parametrize("kind", ["chiral", (0, 1), (0, 2), (1, 2)])
-@pytest.mark.parametrize("mid", [1, 4, 16])
-def test_apply_with_and_without_skipping_32(kind, mid):
+@pytest.mark.parametrize("mid,yz", [(1, 16), (4, 2), (16, 8), (16, 16), (2, 1)])
+def test_apply_with_and_without_skipping_32(kind, mid, yz):
     grid, k = (32, 32, 32), (0.1, 0.2, 0.3)
     n = 32 ** 3
     if kind == "chiral":
@@ -58,7 +61,7 @@ def test_apply_with_and_without_skipping_32(kind, mid):
     u = torch.from_numpy(media.random_vector(4 * n, 11)).to("cuda")
     outs = []
     for vac in (1, 0):
-        with _plan(grid, k, kind, eps, gam, vac, mid) as P:
+        with _plan(grid, k, kind, eps, gam, vac, mid, yz) as P:
             out = torch.empty_like(u)
             P.Ar(u, out)
             outs.append(host(out))
