@@ -17,6 +17,11 @@ legs (the 40-point Gamma-X-M-Gamma-R path of the 128^3 rods, the 32-instance une
 batch), the gradient with central differences at 50 voxels (64^3), the paper's
 band-structure path G-X-M-R-G at 128^3 for both of its media, the chirality
 sweep (64^3), the NFSEP path (64^3) and the CPU oracle.
+
+Every plan (and batch) first autotunes its pass tiling, outside the timed
+regions, with the results cached for the run by grid shape, medium kind and
+vacuum share (NSF_TUNE_CACHE); --no-autotune, or an explicit --mid-cols /
+--yz-cols / --x-rows, keeps the given tiling.
 """
 from __future__ import annotations
 
@@ -25,6 +30,7 @@ import json
 import os
 import platform
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -60,6 +66,15 @@ def make_medium(w):
     if w["kind"] == "scsc":
         return media.spheres_cylinders_chiral(n1)
     return media.rods_pseudochiral(n1)
+
+
+AUTOTUNE = True  # every leg tunes its plans' pass tiling first (outside the timed regions)
+
+
+def tune(obj):
+    """Autotune a plan or batch (per grid shape; NSF_TUNE_CACHE makes repeats free)."""
+    if AUTOTUNE:
+        obj.autotune(reps=5)
 
 
 def batch_instances(name):
@@ -99,6 +114,7 @@ def batch_leg(name, log=sys.stderr):
                 P.set_chiral(m[1], m[2])
             else:
                 P.set_pseudochiral(0, 1, m[1], m[2])
+            tune(P)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st, om, res, stats = P.eigs(nev, seed=kw["seed"] + 1000003 * i, res_tol=kw["res_tol"],
@@ -119,7 +135,7 @@ def batch_leg(name, log=sys.stderr):
                 B.set_pseudochiral(i, 0, 1, m[1], m[2])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        shapes = B.autotune(reps=5)  # tiling per grid shape (set-up, reported apart)
+        shapes = B.autotune(reps=5) if AUTOTUNE else 0  # tiling per grid shape (set-up, reported apart)
         torch.cuda.synchronize()
         t_tune = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -155,6 +171,7 @@ def kpath_warm_leg(log=sys.stderr, nev=10):
     for i, k in enumerate(ks):
         with nsf.Plan(g, k) as P:
             P.set_pseudochiral(0, 1, eps, gam)
+            tune(P)
             Y = torch.empty((nev, 4 * n), dtype=torch.complex128, device="cuda")
             if prev is not None:
                 P.set_start(prev)
@@ -173,6 +190,7 @@ def kpath_warm_leg(log=sys.stderr, nev=10):
         for i in range(len(ks)):
             B.set_pseudochiral(i, 0, 1, eps, gam)
             nsf.nsf_plan_set_option(B.plan(i), nsf.NSF_OPT_WARM_CHAIN, int(i > 0))
+        tune(B)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st, om, res, stats, wave = B.eigs(nev, **kw)
@@ -205,6 +223,7 @@ def gamma_sweep_leg(n1=64, log=sys.stderr, nev=10):
             eps, gam = media.spheres_cylinders_chiral(n1, eps_in=eps_i, eps_out=1.0, gamma=gmm)
             with nsf.Plan((n1, n1, n1), (0.5, 0.0, 0.0)) as P:
                 P.set_chiral(eps, gam)
+                tune(P)
                 P.set_option(nsf.NSF_OPT_VERIFY, 16)  # k on a lattice axis of a cubic structure
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -253,6 +272,7 @@ def band_leg(per_seg, n1=128, log=sys.stderr, nev=10):
         for k in ks:
             with nsf.Plan(grid, tuple(k)) as P:
                 P.set_chiral(eps_d, gam_d)
+                tune(P)
                 P.set_option(nsf.NSF_OPT_VERIFY, 16)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -369,6 +389,7 @@ def extra_workloads(log=sys.stderr):
     n = 128 ** 3
     with nsf.Plan((128, 128, 128), (0.1, 0.2, 0.3)) as P:
         P.set_pseudochiral(0, 1, *media.rods_pseudochiral(128))
+        tune(P)
         u = torch.from_numpy(media.random_vector(4 * n, 0)).to("cuda")
         o = torch.empty_like(u)
         us = median_apply_us(P, u, o)
@@ -380,6 +401,7 @@ def extra_workloads(log=sys.stderr):
                           ("sphere16_eigs", (16, 16, 16), (0.1, 0.2, 0.3))):
         with nsf.Plan(grid, k) as P:
             P.set_chiral(*media.sphere_chiral(grid[0]))
+            tune(P)
             P.eigs(10, res_tol=1e-8, cg_rtol=1e-10)  # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -418,6 +440,7 @@ def grad_leg(nvox, log=sys.stderr, h=1e-6, nev=4):
     vox = np.random.default_rng(1).choice(n, size=nvox, replace=False)
     with nsf.Plan(grid, k) as P:
         P.set_chiral(eps, gam)
+        tune(P)
         Y = torch.empty(nev * 4 * n, dtype=torch.complex128, device="cuda")
         P.eigs(nev, Y=Y, **kw)  # warm-up
         torch.cuda.synchronize()
@@ -449,6 +472,7 @@ def grad_leg(nvox, log=sys.stderr, h=1e-6, nev=4):
     with nsf.Batch([grid] * len(fields), [k] * len(fields)) as B:
         for i, (e, g) in enumerate(fields):
             B.set_chiral(i, e, g)
+        tune(B)
         stb, omb, resb, _, wave = B.eigs(nev, **kw)
     t_fd = time.perf_counter() - t0
     S = omb.sum(axis=1).reshape(2, nvox, 2)
@@ -647,7 +671,10 @@ def main():
     ap.add_argument("--fft-path", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_FFT_PATH)")
     ap.add_argument("--mid-cols", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_MID_COLS)")
     ap.add_argument("--mid-pairs", type=int, default=-1, help="nsf_plan_set_option(NSF_OPT_MID_PAIRS)")
-    ap.add_argument("--autotune", action="store_true", help="autotune the plan's pass tiling first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default pass tiling (every leg autotunes its plans otherwise)")
+    ap.add_argument("--yz-cols", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_YZ_COLS)")
+    ap.add_argument("--x-rows", type=int, default=0, help="nsf_plan_set_option(NSF_OPT_X_ROWS)")
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="only run this many A_r applies plus a 1 GiB device copy (for rocprofv3)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a rocprofv3 kernel-stats table and exit")
@@ -684,6 +711,13 @@ def main():
               "split in z-slabs would need an all-to-all before and after the fused z pass",
               file=sys.stderr)
         sys.exit(2)
+    global AUTOTUNE
+    AUTOTUNE = not args.no_autotune and not args.mid_cols and not args.yz_cols and not args.x_rows
+    if AUTOTUNE and not os.environ.get("NSF_TUNE_CACHE"):
+        # one tuning per grid shape, medium kind and vacuum share for this run
+        fd, cache = tempfile.mkstemp(prefix="nsf_tune_", suffix=".txt")
+        os.close(fd)
+        os.environ["NSF_TUNE_CACHE"] = cache
 
     pool, nproc = None, 1
     if not args.no_cpu and not args.nfsep_only and not args.profile_applies:
@@ -723,8 +757,12 @@ def main():
     else:
         P.set_pseudochiral(0, 1, eps, gam)
 
+    if args.yz_cols:
+        P.set_option(nsf.NSF_OPT_YZ_COLS, args.yz_cols)
+    if args.x_rows:
+        P.set_option(nsf.NSF_OPT_X_ROWS, args.x_rows)
     tuned = None
-    if args.autotune:
+    if AUTOTUNE:
         tuned = P.autotune(reps=5)
         print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
     # ---- isolated A_r apply: per-kernel HIP-event times and the whole apply

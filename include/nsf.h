@@ -243,7 +243,9 @@ typedef struct {
 int nsf_plan_autotune(nsf_plan plan, int reps, nsf_tune* result);
 /* With NSF_TUNE_CACHE naming a text file, nsf_plan_autotune first looks up the
  * grid shape and medium kind there (a hit applies the stored tiling, reports
- * tried = 0 and times nothing) and appends each new result. */
+ * tried = 0 and times nothing) and appends each new result.  With vacuum
+ * skipping (NSF_OPT_VACUUM) the kind column also holds 16 x (1 + the share of
+ * z-pass tiles that are not all vacuum, in tenths): sparse media tune apart. */
 
 /*
  * Caller-provided workspace (for example from PyTorch's caching allocator).

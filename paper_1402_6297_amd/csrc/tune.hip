@@ -9,6 +9,7 @@
 // candidate computes the same transforms; only the arithmetic order of the CG
 // reductions (partials per workgroup) can change, so results agree to rounding.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -54,6 +55,20 @@ int time_apply(nsf_plan p, const double2* u, double2* out, int reps, hipEvent_t 
 }
 
 // NSF_TUNE_CACHE lines: "nsf-tune n1 n2 n3 kind path mid xr yz pairs us_best us_default".
+// Cache key of a plan's medium: its kind, plus 16 x (1 + the share of z-pass
+// tiles at 16 columns that are not all vacuum, in tenths) when vacuum
+// skipping is on, since the best tiling then depends on that share.
+int tune_key(nsf_plan p) {
+  const VacSkip v = vac_of(p);
+  const Geom& g = p->geom;
+  int key = p->medium_kind;
+  if (v.on && p->ztile_cnt[4] >= 0 && g.n1 % 16 == 0) {
+    const double all = (double)(g.n1 / 16) * (double)g.n2;
+    key += 16 * (1 + (int)std::lround(10.0 * p->ztile_cnt[4] / all));
+  }
+  return key;
+}
+
 bool cache_lookup(const Geom& g, int kind, Tiling* t, double* us_best, double* us_dflt) {
   const char* path = std::getenv("NSF_TUNE_CACHE");
   if (!path || !*path) return false;
@@ -105,7 +120,7 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
   {
     Tiling c{};
     double b = 0, d = 0;
-    if (cache_lookup(g, p->medium_kind, &c, &b, &d)) {
+    if (cache_lookup(g, tune_key(p), &c, &b, &d)) {
       apply_tiling(p, c);
       if (result) {
         result->fft_path = c.path;
@@ -205,7 +220,7 @@ int nsf_plan_autotune(nsf_plan p, int reps, nsf_tune* result) {
   const int tried = (int)seen.size();
   apply_tiling(p, best);
   cleanup();
-  cache_store(g, p->medium_kind, best, best_ms * 1e3, dflt_ms * 1e3);
+  cache_store(g, tune_key(p), best, best_ms * 1e3, dflt_ms * 1e3);
   if (result) {
     result->fft_path = best.path;
     result->mid_cols = best.mid;
