@@ -627,7 +627,7 @@ def summarize_trace(d):
     return "\n".join(out)
 
 
-def summarize_pmc(fetch_dir, write_dir, applies, workload):
+def summarize_pmc(fetch_dir, write_dir, applies, workload, tiling):
     """Per-kernel HBM bytes from FETCH_SIZE / WRITE_SIZE runs, calibrated on the
     1 GiB device copy of the same run (known: 1 GiB read, 1 GiB written)."""
     import collections
@@ -654,7 +654,7 @@ def summarize_pmc(fetch_dir, write_dir, applies, workload):
         wb = sum(wr.get(k, [0.0])) / max(len(wr.get(k, [1])), 1) * w_scale
         kernels[k] = {"fetch_bytes": fb, "write_bytes": wb, "launches": len(fe[k])}
     per_apply = sum((v["fetch_bytes"] + v["write_bytes"]) * v["launches"] for v in kernels.values()) / applies
-    return {"workload": workload, "source_hash": kernel_source_hash(), "fetch_scale": f_scale,
+    return {"workload": workload, "source_hash": kernel_source_hash(), "tiling": tiling, "fetch_scale": f_scale,
             "write_scale": w_scale, "kernels": kernels, "bytes_per_apply": per_apply}
 
 
@@ -699,7 +699,9 @@ def main():
         print(summarize_trace(args.summarize_trace))
         return
     if args.summarize_pmc:
-        res = summarize_pmc(*args.summarize_pmc, applies=args.profile_applies or 3, workload=args.workload)
+        tiling = {"mid_cols": args.mid_cols or 16, "yz_cols": args.yz_cols or 16, "x_rows": args.x_rows or 4}
+        res = summarize_pmc(*args.summarize_pmc, applies=args.profile_applies or 3, workload=args.workload,
+                            tiling=tiling)
         path = os.path.join(ROOT, "profiles", f"ar_apply_traffic_{args.workload}.json")
         with open(path, "w") as f:
             json.dump(res, f, indent=1)
@@ -792,7 +794,10 @@ def main():
     tpath = os.path.join(ROOT, "profiles", f"ar_apply_traffic_{args.workload}.json")
     if os.path.exists(tpath):
         t = json.load(open(tpath))
-        if t.get("source_hash") == kernel_source_hash() and args.fft_path == 0:
+        used = {"mid_cols": tuned["mid_cols"], "yz_cols": tuned["yz_cols"], "x_rows": tuned["x_rows"]} if tuned else \
+            {"mid_cols": args.mid_cols or 16, "yz_cols": args.yz_cols or 16, "x_rows": args.x_rows or 4}
+        # the counters hold for these kernels at this tiling only
+        if t.get("source_hash") == kernel_source_hash() and args.fft_path == 0 and t.get("tiling") == used:
             traffic = round(t["bytes_per_apply"])
     print(f"[bench] A_r apply {apply_ms * 1e3:.1f} us, {apply_gbps:.0f} GB/s algorithmic; "
           f"kernels (us): {[round(x * 1e3, 1) for x in pass_ms]}", file=sys.stderr, flush=True)
