@@ -238,9 +238,9 @@ __global__ __launch_bounds__(384) void k_fz_mid(Geom g, Tables t, MediumView med
 // vs > 0 (vacuum skipping): the workgroups cover only the tiles listed in
 // med.ztiles (a tile is P columns of one y; listed when one of its voxels is
 // not vacuum), the constitutive step scales by vs = 1 / n3 instead of 1 / n
-// (the forward x pass applies 1 / (n1 n2)), and a column left out keeps its
-// input, which is what the inverse z, identity, forward z sequence scaled by
-// 1 / n3 returns there.  The partial sums then hold Re f^* (M - I) f / n; the
+// (the forward y and x passes apply 1 / n2 and 1 / n1), and a column left out
+// keeps its input, which is what the inverse z, identity, forward z sequence
+// scaled by 1 / n3 returns there.  The partial sums then hold Re f^* (M - I) f / n; the
 // first CG pass adds |p|^2 = sum |f|^2 / n.
 template <int N1, int N2, bool BT = false, bool PQ = false>
 __global__ __launch_bounds__(256) void k_fz_pair(Geom g, Tables t, MediumView med,
@@ -672,7 +672,7 @@ __global__ __launch_bounds__(384) void k_fx_inv_synth(Geom g, Tables t, const do
 // NOPQ (with CG): the q-free schedule; r = r - alpha q in place of q, with
 // alpha = rr / pap from the CG state (0 when pap is not positive: the step
 // kernel then stops the solve with a breakdown).
-// ps scales the projected result (1 / (n1 n2) after a vacuum-skipping z pass, else 1).
+// ps scales the projected result (1 / n1 after vacuum-skipping y and z passes, else 1).
 template <int N1, int N2, int PART, bool CG = false, bool BT = false, bool NOPQ = false>
 __global__ __launch_bounds__(384) void k_fx_fwd_proj(Geom g, Tables t, const double2* __restrict__ fld,
                                                      double2* __restrict__ out, int R,

@@ -159,8 +159,8 @@ int fast_yz_cols(const Geom& g, int axis);
 // vac_scale > 0 (vacuum skipping, field-pair kernel only): only the
 // med.ztiles tiles are transformed (vac_tiles workgroup triples: the listed
 // count, or the largest over a batch), scaled by vac_scale = 1 / n3; the
-// partials hold Re f^* (M - I) f / n.  The forward x pass must then scale by
-// 1 / (n1 n2) (pscale).
+// partials hold Re f^* (M - I) f / n.  The forward y and x passes must then
+// scale by 1 / n2 and 1 / n1 (launch_fast_yz ysc, pscale).
 hipError_t launch_fast_z_mid(const Geom& g, const Tables& t, const MediumView& med, double2* fld,
                              int P_want, const int* skip, hipStream_t s,
                              const struct InstDesc* insts = nullptr, int ninst = 1,
