@@ -130,3 +130,22 @@ def test_shared_batch_with_air_and_spheres_16():
             st1, om1, _, _ = P.eigs(6, **kw)
         assert st1 == nsf.NSF_OK
         assert np.all(np.abs(om[i] - om1) <= 1e-10 * om1)
+
+
+def test_shared_batch_pseudochiral_rods_16():
+    """Pseudochiral rods of different radii sharing launches, against plain solves
+    without skipping."""
+    grid = (16, 16, 16)
+    ks = [(0.1, 0.2, 0.3), (0.3, 0.1, 0.2), (0.2, 0.05, 0.1)]
+    meds = [media.rods_pseudochiral(16, radius=r) for r in (0.15, 0.25, 0.35)]
+    kw = dict(res_tol=1e-10, cg_rtol=1e-12)
+    with nsf.Batch([grid] * 3, ks) as B:
+        for i, (e, g) in enumerate(meds):
+            B.set_pseudochiral(i, 0, 1, e, g)
+        st, om, res, stats, wave = B.eigs(6, **kw)
+    assert st == nsf.NSF_OK and res.max() <= 1e-10 and wave == 3
+    for i in range(3):
+        with _plan(grid, ks[i], (0, 1), *meds[i], 0) as P:
+            st1, om1, _, _ = P.eigs(6, **kw)
+        assert st1 == nsf.NSF_OK
+        assert np.all(np.abs(om[i] - om1) <= 1e-10 * om1)
