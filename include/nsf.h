@@ -176,9 +176,10 @@ enum {
                             instead of reading and writing x in every
                             iteration (128 n bytes less per iteration,
                             16 x 64 n bytes of device memory more); the
-                            residual recurrence is unchanged, so iterations
-                            and residuals are the same and x differs only in
-                            rounding.  0: x updated every iteration       */
+                            residual recurrence is unchanged, and a fold
+                            performs the same multiply-adds in the same
+                            order, so iterations, residuals and x are the
+                            same.  0: x updated every iteration           */
   NSF_OPT_VACUUM = 15     /* 1 (default): with a chiral or pseudochiral medium
                             on the two-level passes, the field-pair z pass
                             transforms only the tiles (P pencil columns of
