@@ -59,10 +59,11 @@ int time_apply(nsf_plan p, const double2* u, double2* out, int reps, hipEvent_t 
 // tiles at 16 columns that are not all vacuum, in tenths) when vacuum
 // skipping is on, since the best tiling then depends on that share.
 int tune_key(nsf_plan p) {
-  const VacSkip v = vac_of(p);
   const Geom& g = p->geom;
   int key = p->medium_kind;
-  if (v.on && p->ztile_cnt[4] >= 0 && g.n1 % 16 == 0) {
+  // (from the plan's medium and options, not from the tiling being tried)
+  const bool vac = p->opt_vacuum && p->d_ztiles && (key == kMedChiral || key == kMedPseudo);
+  if (vac && p->ztile_cnt[4] >= 0 && g.n1 % 16 == 0) {
     const double all = (double)(g.n1 / 16) * (double)g.n2;
     key += 16 * (1 + (int)std::lround(10.0 * p->ztile_cnt[4] / all));
   }
