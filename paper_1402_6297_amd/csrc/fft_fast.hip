@@ -37,6 +37,23 @@ struct Split {
   static constexpr int D = (N1 + N2 - 1) / N2;  // step-2 transforms per thread
 };
 
+// The y/z passes exchange between the two steps in PH phases of up to RP rows
+// k1 (each of N2 elements), so that their LDS tile holds RP rows, not N1.  The
+// forward passes (S < 0) take two phases when a thread has two or more step-2
+// transforms: half the LDS per pencil, twice the workgroups per CU (LDS, not
+// registers, limits them), measured faster; the inverse passes ran slower so
+// and keep one.
+struct YzPhases {
+  int PH, DP, RP, rows;
+};
+__host__ __device__ constexpr YzPhases yz_phases(int N1, int N2, int S) {
+  const int D = (N1 + N2 - 1) / N2;
+  const int PH = D > 1 && S < 0 ? 2 : 1;
+  const int DP = (D + PH - 1) / PH;
+  const int RP = DP * N2;
+  return YzPhases{PH, DP, RP, RP < N1 ? RP : N1};
+}
+
 // ------------------------------------------------------------ y / z passes
 // P pencils (consecutive x) per workgroup, N2 threads per pencil, lane order
 // p fastest.  LDS tile[(e) * P + p], e = n2 + N2 k1.
@@ -94,24 +111,33 @@ __global__ __launch_bounds__(256) void k_fyz(Geom g, Tables t, int axis, double2
   }
   __syncthreads();  // twiddle table ready
   step1<N1, N2, S>(v, n2, twl);
+  constexpr YzPhases Y = yz_phases(N1, N2, S);
 #pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) tile[(n2 + N2 * k1) * P + p] = v[k1];
-  __syncthreads();
+  for (int ph = 0; ph < Y.PH; ++ph) {
+    if (ph > 0) __syncthreads();  // the previous phase's rows have been read
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const int k1 = n2 + d * N2;
-    if (k1 < N1) {
-      double2 u[N2];
+    for (int kl = 0; kl < Y.RP; ++kl) {
+      const int k1 = ph * Y.RP + kl;
+      if (k1 < N1) tile[(n2 + N2 * kl) * P + p] = v[k1];
+    }
+    __syncthreads();
 #pragma unroll
-      for (int m = 0; m < N2; ++m) u[m] = tile[(m + N2 * k1) * P + p];
-      reg_dft<N2, S>(u);
+    for (int dd = 0; dd < Y.DP; ++dd) {
+      const int k1 = n2 + (ph * Y.DP + dd) * N2;
+      if (ph * Y.DP + dd < D && k1 < N1) {
+        const int kl = n2 + dd * N2;  // k1's row in this phase
+        double2 u[N2];
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) {
-        const int j = k1 + N1 * k2;
-        double2 x = u[k2];
-        if (post_twist) x = cscale(cmul(twist_at(t.twist, g, i1_0 + p, io, j), x), rs);
-        if (ysc > 0.0) x = cscale(x, ysc);
-        F[j * stride] = x;
+        for (int m = 0; m < N2; ++m) u[m] = tile[(m + N2 * kl) * P + p];
+        reg_dft<N2, S>(u);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const int j = k1 + N1 * k2;
+          double2 x = u[k2];
+          if (post_twist) x = cscale(cmul(twist_at(t.twist, g, i1_0 + p, io, j), x), rs);
+          if (ysc > 0.0) x = cscale(x, ysc);
+          F[j * stride] = x;
+        }
       }
     }
   }
@@ -917,7 +943,7 @@ hipError_t launch_fast_yz(const Geom& g, const Tables& t, int axis, int dir, int
   const long long groups = ysc > 0.0 ? nxg : g.n1 / P;
   const dim3 grid((unsigned)(groups * other), (unsigned)nf, (unsigned)ninst);
   const dim3 block(P * cfg.N2);
-  const size_t lds = sizeof(double2) * (size_t)(N + N * P);
+  const size_t lds = sizeof(double2) * (size_t)(N + yz_phases(cfg.N1, cfg.N2, dir).rows * cfg.N2 * P);
 #define L_YZ(A, B)                                                                                   \
   if (insts && dir > 0)                                                                              \
     hipLaunchKernelGGL((k_fyz<A, B, +1, true>), grid, block, lds, s, g, t, axis, fld, P, post_twist, \
