@@ -104,9 +104,10 @@ enum {
                                x and fused z passes where possible          */
   NSF_OPT_MID_COLS = 2,  /* pencils per workgroup of the fused z pass: 1..16,
                             power of two (default 16)                         */
-  NSF_OPT_CG_GRAPH = 3,  /* 1: the eigensolver captures one CG iteration of all
-                            unfinished instances as a HIP graph and replays it
-                            (default); 0: launches every kernel each iteration */
+  NSF_OPT_CG_GRAPH = 3,  /* 1: the eigensolver captures 1, 2, 4 and 8 CG
+                            iterations of all unfinished instances as HIP
+                            graphs and replays them (default); 0: launches
+                            every kernel each iteration                      */
   NSF_OPT_X_ROWS = 4,    /* grid rows per workgroup of the two-level x passes:
                             1, 2 or 4 (default 4; lowered where it does not fit) */
   NSF_OPT_YZ_COLS = 5,   /* pencils per workgroup of the two-level y / z passes:

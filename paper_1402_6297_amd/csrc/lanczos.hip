@@ -219,13 +219,20 @@ int cg_iteration_all(std::vector<Group>& groups, hipStream_t s) {
 // private stream of default priority, ordered after the caller's stream by an
 // event; the graph holds kernel nodes only.
 struct CgGraph {
+  static constexpr int kSizes = 4;  // graphs of 1, 2, 4 and 8 iterations
   hipStream_t cs = nullptr;
   hipEvent_t ev = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec[kSizes] = {};
   std::vector<const void*> sig;
   int captures = 0;
+  void drop() {
+    for (hipGraphExec_t& e : exec) {
+      if (e) hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+  }
   ~CgGraph() {
-    if (exec) hipGraphExecDestroy(exec);
+    drop();
     if (ev) hipEventDestroy(ev);
     if (cs) hipStreamDestroy(cs);
   }
@@ -245,6 +252,10 @@ struct StreamSwap {
   }
 };
 
+// The graphs of 2^k consecutive CG iterations (k < kSizes) of the current set
+// of unfinished runs, captured again when that set changes.  A chunk of c
+// iterations replays the graphs of c's binary digits: a graph launch costs
+// about as much host-to-GPU latency as one iteration's gaps otherwise would.
 int cg_graph_ready(CgGraph& cg, std::vector<Group>& groups, std::vector<Run*>& act) {
   nsf_plan p0 = act[0]->p;
   std::vector<const void*> sig;
@@ -252,21 +263,25 @@ int cg_graph_ready(CgGraph& cg, std::vector<Group>& groups, std::vector<Run*>& a
     sig.push_back(reinterpret_cast<const void*>((size_t)G.act.size()));
     for (Run* r : G.act) sig.push_back(r->p);
   }
-  if (cg.exec && sig == cg.sig) return NSF_OK;
-  if (cg.exec) NSF_HIP(p0, hipGraphExecDestroy(cg.exec));
-  cg.exec = nullptr;
-  NSF_HIP(p0, hipStreamBeginCapture(cg.cs, hipStreamCaptureModeRelaxed));
-  const int rc = cg_iteration_all(groups, cg.cs);
-  hipGraph_t graph = nullptr;
-  const hipError_t e = hipStreamEndCapture(cg.cs, &graph);
-  if (rc) {
-    if (graph) hipGraphDestroy(graph);
-    return rc;
+  if (cg.exec[0] && sig == cg.sig) return NSF_OK;
+  cg.drop();
+  for (int k = 0; k < CgGraph::kSizes; ++k) {
+    NSF_HIP(p0, hipStreamBeginCapture(cg.cs, hipStreamCaptureModeRelaxed));
+    int rc = NSF_OK;
+    for (int i = 0; i < (1 << k) && !rc; ++i) rc = cg_iteration_all(groups, cg.cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cg.cs, &graph);
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      cg.drop();
+      return rc;
+    }
+    NSF_HIP(p0, e);
+    const hipError_t ei = hipGraphInstantiate(&cg.exec[k], graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) cg.drop();
+    NSF_HIP(p0, ei);
   }
-  NSF_HIP(p0, e);
-  const hipError_t ei = hipGraphInstantiate(&cg.exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
-  NSF_HIP(p0, ei);
   cg.sig = sig;
   cg.captures += 1;
   return NSF_OK;
@@ -343,10 +358,11 @@ int cg_all(std::vector<Group>& groups, std::vector<Run*>& act, hipStream_t s, Cg
   std::vector<int> it_prev(act.size(), 0);
   int chunk = 4;
   for (;;) {
-    for (int c = 0; c < chunk; ++c) {
-      if (graph) {
-        NSF_HIP(act[0]->p, hipGraphLaunch(cgg->exec, ws));
-      } else {
+    if (graph) {
+      for (int k = CgGraph::kSizes - 1, left = chunk; k >= 0; --k)
+        for (; left >= (1 << k); left -= 1 << k) NSF_HIP(act[0]->p, hipGraphLaunch(cgg->exec[k], ws));
+    } else {
+      for (int c = 0; c < chunk; ++c) {
         const int rc = cg_iteration_all(groups, ws);
         if (rc) return rc;
       }
