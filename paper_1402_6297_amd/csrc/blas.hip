@@ -724,33 +724,18 @@ hipError_t launch_multi_dot2(const double2* V, long long ld, int m, const double
   return hipGetLastError();
 }
 
-// z = b - r - sum_k c_k AV_{idx_k}: the image A_r x of a CG solution from its
-// right-hand side b, final residual r and the projected start (c as for
-// launch_cg_init: m coefficients, then the m indices as doubles in .x).
-__global__ void k_cg_image(const double2* __restrict__ b, const double2* __restrict__ r,
-                           const double2* __restrict__ AV, long long ld, int m, const double2* __restrict__ c,
-                           double2* __restrict__ z, long long len) {
-  __shared__ double2 cs[512];
-  __shared__ int ix[512];
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    cs[i] = c[i];
-    ix[i] = (int)c[m + i].x;
-  }
-  __syncthreads();
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
-       i += (long long)gridDim.x * blockDim.x) {
-    double2 v = csub(b[i], r[i]);
-#pragma unroll 4
-    for (int j = 0; j < m; ++j) v = csub(v, cmul(cs[j], AV[ix[j] * ld + i]));
-    z[i] = v;
-  }
-}
+// The Lanczos step's updates fused with B_r w and the two inner products that
+// follow them (launch_step_fused).  B_r at frequency f is i / sigma_f times
+// (y_c, y_d, -y_a, -y_b), sigma_f^2 = |lambda_1|^2 + |lambda_2|^2 + |lambda_3|^2.
+constexpr int kStepParts = 2048;
 
-// w -= sum_k c_k V_{idx_k} and z -= sum_k c_k V2_{idx_k} (c: m coefficients, then
-// the m indices as doubles in .x): a Gram-Schmidt update over a few basis columns.
-__global__ void k_sparse_axpy2(const double2* __restrict__ V, const double2* __restrict__ V2, long long ld,
-                               int m, const double2* __restrict__ c, double2* __restrict__ w,
-                               double2* __restrict__ z, long long len) {
+__global__ __launch_bounds__(kRedThreads) void k_step_fused(Geom g, Tables t, int mode, double2* w,
+                                                            double2* __restrict__ z, double2* b,
+                                                            const double2* __restrict__ r,
+                                                            const double2* __restrict__ V,
+                                                            const double2* __restrict__ AV, long long ld,
+                                                            int m, const double2* __restrict__ c,
+                                                            double2* partial) {
   __shared__ double2 cs[512];
   __shared__ int ix[512];
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
@@ -758,31 +743,66 @@ __global__ void k_sparse_axpy2(const double2* __restrict__ V, const double2* __r
     ix[i] = (int)c[m + i].x;
   }
   __syncthreads();
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
-       i += (long long)gridDim.x * blockDim.x) {
-    double2 a = w[i], b = z[i];
+  const long long n = g.n;
+  double2 a0 = make_double2(0, 0), a1 = make_double2(0, 0);
+  for (long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x; f < n;
+       f += (long long)gridDim.x * blockDim.x) {
+    double2 wv[4], zv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long i = q * n + f;
+      if (mode == 0) {
+        double2 v = csub(b[i], r[i]);
 #pragma unroll 4
-    for (int j = 0; j < m; ++j) {
-      a = csub(a, cmul(cs[j], V[ix[j] * ld + i]));
-      b = csub(b, cmul(cs[j], V2[ix[j] * ld + i]));
+        for (int j = 0; j < m; ++j) v = csub(v, cmul(cs[j], AV[ix[j] * ld + i]));
+        zv[q] = v;
+        wv[q] = w[i];
+      } else {
+        double2 a = w[i], e = z[i];
+#pragma unroll 4
+        for (int j = 0; j < m; ++j) {
+          a = csub(a, cmul(cs[j], V[ix[j] * ld + i]));
+          e = csub(e, cmul(cs[j], AV[ix[j] * ld + i]));
+        }
+        wv[q] = a;
+        zv[q] = e;
+      }
     }
-    w[i] = a;
-    z[i] = b;
+    const int i1 = (int)(f % g.n1);
+    const int i2 = (int)((f / g.n1) % g.n2);
+    const int i3 = (int)(f / ((long long)g.n1 * g.n2));
+    const double s2 = cabs2(t.lam[i1]) + cabs2(t.lam[g.n1 + i2]) + cabs2(t.lam[g.n1 + g.n2 + i3]);
+    const double is = 1.0 / sqrt(s2);
+    const double2 bv[4] = {cscale(cmuli(wv[2]), is), cscale(cmuli(wv[3]), is), cscale(cmuli(wv[0]), -is),
+                           cscale(cmuli(wv[1]), -is)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long i = q * n + f;
+      if (mode == 1) w[i] = wv[q];
+      z[i] = zv[q];
+      b[i] = bv[q];
+      a0 = cadd(a0, cmulc(wv[q], zv[q]));
+      a1 = cadd(a1, cmulc(wv[q], bv[q]));
+    }
+  }
+  a0 = block_sum(a0);
+  a1 = block_sum(a1);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = a0;
+    partial[kStepParts + blockIdx.x] = a1;
   }
 }
 
-hipError_t launch_sparse_axpy2(const double2* V, const double2* V2, long long ld, int m, const double2* c,
-                               double2* w, double2* z, long long len, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  if (m > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sparse_axpy2, dim3(ew_grid(len)), dim3(256), 0, s, V, V2, ld, m, c, w, z, len);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_image(const double2* b, const double2* r, const double2* AV, long long ld, int m,
-                           const double2* c, double2* z, long long len, hipStream_t s) {
-  if (m < 0 || m > 512 || (m > 0 && (!AV || !c))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_image, dim3(ew_grid(len)), dim3(256), 0, s, b, r, AV, ld, m, c, z, len);
+hipError_t launch_step_fused(const Geom& g, const Tables& t, int mode, double2* w, double2* z, double2* b,
+                             const double2* r, const double2* V, const double2* AV, long long ld, int m,
+                             const double2* c, double2* partial, double2* res2, hipStream_t s) {
+  if (m < 0 || m > 512 || (m > 0 && (!AV || !c)) || (mode == 1 && m > 0 && !V) || (mode == 0 && !r))
+    return hipErrorInvalidValue;
+  const int nb = (int)std::min<long long>((g.n + kRedThreads - 1) / kRedThreads, kStepParts);
+  hipLaunchKernelGGL(k_step_fused, dim3(nb), dim3(kRedThreads), 0, s, g, t, mode, w, z, b, r, V, AV, ld, m, c,
+                     partial);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, partial, nb, res2);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, partial + kStepParts, nb, res2 + 1);
   return hipGetLastError();
 }
 

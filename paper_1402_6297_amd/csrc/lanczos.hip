@@ -706,12 +706,12 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
     // w^* A_r w, w^* B_r w.
     for (Run* r : act) {
       nsf_plan p = r->p;
-      NSF_HIP(p, launch_cg_image(r->bv, p->d_cg, r->AV, r->len, r->start_m, p->d_coef, r->z, r->len, s));
-      NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, r->w, r->bv, nullptr, s));
+      // z, B_r w into bv, ||w||_A^2 = w^* z and w^* B_r w into slots 0 and 1
+      NSF_HIP(p, launch_step_fused(p->geom, p->tabs, 0, r->w, r->z, r->bv, p->d_cg, nullptr, r->AV, r->len,
+                                   r->start_m, p->d_coef, p->d_partial, p->d_res, s));
+      NSF_HIP(p, hipMemcpyAsync(p->h_res, p->d_res, sizeof(double2) * 2, hipMemcpyDeviceToHost, s));
       NSF_HIP(p, launch_multi_dot2(r->V, r->len, r->nb, r->z, r->bv, r->len, p->d_partial, p->d_coef, s));
       NSF_HIP(p, hipMemcpyAsync(p->h_res + 64, p->d_coef, sizeof(double2) * 2 * r->nb, hipMemcpyDeviceToHost, s));
-      if ((rc = dot_async(p, r->w, r->z, r->len, 0))) return fail(rc);   // ||w||_A^2
-      if ((rc = dot_async(p, r->w, r->bv, r->len, 1))) return fail(rc);  // w^* B_r w
     }
     NSF_HIP(act[0]->p, hipStreamSynchronize(s));
     // Sparse Gram-Schmidt: only the coefficients c_i = v_i^* A_r w above
@@ -769,10 +769,10 @@ int run_engine(std::vector<Run*>& runs, hipStream_t s) {
           hc[ms + k] = make_double2((double)sel[a][k], 0.0);
         }
         NSF_HIP(p, hipMemcpyAsync(p->d_coef, hc, sizeof(double2) * 2 * ms, hipMemcpyHostToDevice, s));
-        NSF_HIP(p, launch_sparse_axpy2(r->V, r->AV, r->len, ms, p->d_coef, r->w, r->z, r->len, s));
-        NSF_HIP(p, launch_apply_Br(p->geom, p->tabs, r->w, r->bv, nullptr, s));
-        if ((rc = dot_async(p, r->w, r->z, r->len, 2))) return fail(rc);   // ||w||_A^2 after
-        if ((rc = dot_async(p, r->w, r->bv, r->len, 3))) return fail(rc);  // w^* B_r w after
+        // the update, B_r w, and ||w||_A^2, w^* B_r w after it into slots 2 and 3
+        NSF_HIP(p, launch_step_fused(p->geom, p->tabs, 1, r->w, r->z, r->bv, nullptr, r->V, r->AV, r->len, ms,
+                                     p->d_coef, p->d_partial, p->d_res + 2, s));
+        NSF_HIP(p, hipMemcpyAsync(p->h_res + 2, p->d_res + 2, sizeof(double2) * 2, hipMemcpyDeviceToHost, s));
         sparse.push_back(r);
       }
     }

@@ -325,14 +325,18 @@ hipError_t launch_multi_dot(const double2* V, long long ld, int m, const double2
 // out[0..m) = V^* w1 and out[m..2m) = V^* w2 in one pass over V (m <= 256).
 hipError_t launch_multi_dot2(const double2* V, long long ld, int m, const double2* w1, const double2* w2,
                              long long len, double2* partial, double2* out, hipStream_t s);
-// z = b - r - sum_k c_k AV_{idx_k} (c, idx laid out as for launch_cg_init; m <= 512):
-// A_r x for a CG solution x of A_r x = b started from the projected guess.
-hipError_t launch_cg_image(const double2* b, const double2* r, const double2* AV, long long ld, int m,
-                           const double2* c, double2* z, long long len, hipStream_t s);
-// w -= sum_k c_k V_{idx_k}, z -= sum_k c_k V2_{idx_k} (c: m coefficients then m
-// indices as doubles in .x, device; m <= 512).
-hipError_t launch_sparse_axpy2(const double2* V, const double2* V2, long long ld, int m, const double2* c,
-                               double2* w, double2* z, long long len, hipStream_t s);
+// One pass over the frequencies f of a Lanczos step's 4n vectors (components
+// f, f + n, f + 2n, f + 3n; c, idx as for launch_cg_init, m <= 512):
+//   mode 0: z = b - r - sum_k c_k AV_{idx_k}, the image A_r x of a CG solution x
+//           of A_r x = b started from the projected guess (r its final residual);
+//   mode 1: w -= sum_k c_k V_{idx_k}, z -= sum_k c_k AV_{idx_k} (a Gram-Schmidt
+//           update over a few basis columns);
+// then b = B_r w (b may be the right-hand side read in mode 0: each thread reads
+// its frequency before writing it), res2[0] = w^* z and res2[1] = w^* B_r w
+// (device; the partial sums use `partial`, 2 x 2048 slots).
+hipError_t launch_step_fused(const Geom& g, const Tables& t, int mode, double2* w, double2* z, double2* b,
+                             const double2* r, const double2* V, const double2* AV, long long ld, int m,
+                             const double2* c, double2* partial, double2* res2, hipStream_t s);
 // w = wscale (w - sum_i c[i] V_i) and, if V2 is given, z -= sum_i c[i] V2_i
 // (c on device, m <= 512).
 hipError_t launch_multi_axpy(const double2* V, long long ld, int m, const double2* c, double2* w,
